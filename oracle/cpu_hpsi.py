@@ -1,0 +1,79 @@
+"""ctypes wrapper of the C/OpenMP oracle H psi (TEST INFRASTRUCTURE ONLY).
+
+``build()`` compiles ``cpu_hpsi.c`` with gcc; ``hpsi_blocks`` applies the
+operator to states in the block layout [nblk, np, B] for CPU timing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from . import stencil
+from .grid import neighbour_table
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cpu_hpsi.c")
+_LIB = os.path.join(_HERE, "libcpu_hpsi.so")
+
+
+def build() -> str:
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp",
+           "-fPIC", "-shared", "-o", _LIB, _SRC]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+def _lib():
+    if not os.path.exists(_LIB):
+        raise RuntimeError(f"{_LIB} not built; run oracle.cpu_hpsi.build()")
+    lib = ctypes.CDLL(_LIB)
+    f = lib.oracle_hpsi_f64
+    P = ctypes.c_void_p
+    f.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
+                  ctypes.c_double, P, P, P, ctypes.c_int, P, P, P, P, P]
+    f.restype = None
+    return f
+
+
+class CpuHamiltonian:
+    """Holds the flattened tables of an oracle Hamiltonian for the C kernel."""
+
+    def __init__(self, H):
+        g = H.g
+        self.np = g.np
+        self.M = g.M
+        self.h = g.h
+        self.nbr = np.ascontiguousarray(neighbour_table(g).reshape(g.np, -1))
+        self.c = stencil.fd_weights(g.M)
+        self.vloc = np.ascontiguousarray(H.vloc, dtype=np.float64)
+        ps = H.proj
+        if ps is not None and ps.nat:
+            self.nat = ps.nat
+            lens = [len(i) for i in ps.idx]
+            self.sph_ptr = np.zeros(self.nat + 1, dtype=np.int64)
+            self.sph_ptr[1:] = np.cumsum(lens)
+            self.sph_idx = np.ascontiguousarray(np.concatenate(ps.idx).astype(np.int64))
+            self.gamma = np.ascontiguousarray(np.concatenate(ps.gamma, axis=0))
+            self.D = np.ascontiguousarray(ps.D, dtype=np.float64)
+        else:
+            self.nat = 0
+            self.sph_ptr = np.zeros(1, dtype=np.int64)
+            self.sph_idx = np.zeros(1, dtype=np.int64)
+            self.gamma = np.zeros((1, 4))
+            self.D = np.zeros((1, 4))
+        self._f = _lib()
+
+    def hpsi_blocks(self, psi_blk: np.ndarray) -> np.ndarray:
+        nblk, np_, B = psi_blk.shape
+        assert np_ == self.np and B <= 64
+        x = np.ascontiguousarray(psi_blk, dtype=np.float64)
+        y = np.empty_like(x)
+        proj = np.empty((max(self.nat, 1), 4, B))
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._f(self.np, nblk, B, ptr(self.nbr), self.M, ptr(self.c), self.h,
+                ptr(self.vloc), ptr(x), ptr(y), self.nat, ptr(self.sph_ptr),
+                ptr(self.sph_idx), ptr(self.gamma), ptr(self.D), ptr(proj))
+        return y

@@ -1,0 +1,187 @@
+"""Oracle: one RMM-DIIS eigensolver step with the filter preconditioner
+(TEST INFRASTRUCTURE ONLY).
+
+Sec. 3: each SCF iteration runs a fixed number of RMM-DIIS iterations on the
+Kohn-Sham Hamiltonian, preconditioned with a low-pass filter; the method needs
+H psi, orthogonalisation and subspace diagonalisation (Sec. 6).  Sec. 9: a
+block of states stops iterating only when every state of the block is below
+the threshold.  The RMM-DIIS body itself is only cited by the paper; the
+reading taken here is:
+
+  1. H psi for all states; Rayleigh-Ritz (eqs. 9-10) gives eps_k.
+  2. Per state: R0 = H psi0 - eps0 psi0 (eps0 the Rayleigh quotient),
+     d = K R0; the trial step lambda minimises the Rayleigh quotient of
+     psi0 + lambda d (lowest eigenpair (x, y) of the 2x2 problem in the
+     basis {psi0, d/||d||}, lambda = y / (x ||d||)); psi1 = psi0 + lambda d,
+     H psi1 = H psi0 + lambda H d.  (Minimising the residual norm along d
+     instead moves random starting states up the spectrum.)
+  3. For j = 1 .. m-1: with residuals R_i = H psi_i - eps_i psi_i of every
+     iterate so far, minimise ||sum c R|| / ||sum c psi|| over the history
+     (generalised eigenproblem A c = mu B c, lowest mu).  The history is
+     expressed in the basis {psi_L, psi_i - psi_L} (L the latest iterate), and
+     c is normalised so its first component is one (coefficients on the
+     original iterates then sum to one).  psibar, H psibar and Rbar follow
+     from c; d = K Rbar; psi_{j+1} = psibar + lambda d (lambda from step 2),
+     H psi_{j+1} = H psibar + lambda H d.
+  4. Orthonormalise all states (Cholesky, eq. 8).
+A state whose lambda is exactly zero keeps psi0.  The filter is
+K r_p = alpha r_p + (1 - alpha)/6 sum of the six nearest neighbours (zero
+outside the domain), alpha = 1/2.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import scipy.linalg
+
+from .grid import Grid, neighbour_table
+from .linalg import dots, orthonormalize, rayleigh_ritz
+
+
+@dataclasses.dataclass
+class Options:
+    m: int = 3               # iterates built per step (H d applications)
+    alpha: float = 0.5       # filter centre weight
+    tol: float = 1e-6        # residual-norm threshold
+    block: int = 32          # block size for the stopping rule
+    block_stop: bool = True
+
+
+def filter_precond(g: Grid, r: np.ndarray, nbr: Optional[np.ndarray] = None,
+                   alpha: float = 0.5) -> np.ndarray:
+    """K r = alpha r + (1 - alpha)/6 (sum of the 6 nearest neighbours)."""
+    if nbr is None:
+        nbr = neighbour_table(g)
+    x = np.atleast_2d(r)
+    xp = np.concatenate([x, np.zeros((x.shape[0], 1))], axis=1)
+    idx = np.where(nbr[:, :, :, 0] < 0, g.np, nbr[:, :, :, 0])   # m = 1
+    s = np.zeros_like(x)
+    for a in range(3):
+        s = s + (xp[:, idx[:, a, 0]] + xp[:, idx[:, a, 1]])
+    out = alpha * x + (1.0 - alpha) / 6.0 * s
+    return out if r.ndim == 2 else out[0]
+
+
+def diis_coefficients(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Lowest generalised eigenvector of A c = mu B c with c[0] = 1;
+    falls back to c = e_0 when B is not positive definite."""
+    try:
+        mu, vec = scipy.linalg.eigh(A, B)
+    except np.linalg.LinAlgError:
+        vec = None
+    c = np.zeros(A.shape[0])
+    c[0] = 1.0
+    if vec is None:
+        return c
+    v = vec[:, 0]
+    if not np.isfinite(v).all() or v[0] == 0.0:
+        return c
+    return v / v[0]
+
+
+def trial_lambda(a11, a12, a22, b11, b12, b22) -> float:
+    """Step length minimising the Rayleigh quotient on span{psi, d}; the
+    entries are <psi|H psi>, <psi|H d>, <d|H d>, <psi|psi>, <psi|d>, <d|d>."""
+    if not b22 > 0.0:
+        return 0.0
+    s = 1.0 / np.sqrt(b22)
+    A = np.array([[a11, a12 * s], [a12 * s, a22 * s * s]])
+    B = np.array([[b11, b12 * s], [b12 * s, 1.0]])
+    try:
+        mu, vec = scipy.linalg.eigh(A, B)
+    except np.linalg.LinAlgError:
+        return 0.0
+    x, y = vec[0, 0], vec[1, 0]
+    if x == 0.0 or not np.isfinite(x) or not np.isfinite(y):
+        return 0.0
+    return float(y / x * s)
+
+
+def rmmdiis_step(H, psi: np.ndarray, opts: Options):
+    """One eigensolver step.  psi [N, np] orthonormal on entry.
+    Returns dict(psi, eig, resnorm, active, lam)."""
+    dv = H.dv
+    g = H.g
+    nbr = H.nbr
+    hpsi = H.apply(psi)
+    eig, _, psi, hpsi = rayleigh_ritz(psi, hpsi, dv)
+    N = psi.shape[0]
+
+    eps0 = dots(psi, hpsi, dv) / dots(psi, psi, dv)
+    R0 = hpsi - eps0[:, None] * psi
+    res = np.sqrt(dots(R0, R0, dv))
+
+    active = np.ones(N, dtype=bool)
+    if opts.block_stop:
+        for b0 in range(0, N, opts.block):
+            if np.all(res[b0:b0 + opts.block] < opts.tol):
+                active[b0:b0 + opts.block] = False
+    lam = np.zeros(N)
+    if active.any():
+        A = np.nonzero(active)[0]
+        p0, h0, r0, e0 = psi[A], hpsi[A], R0[A], eps0[A]
+        d = filter_precond(g, r0, nbr, opts.alpha)
+        hd = H.apply(d)
+        a11 = dots(p0, h0, dv)
+        a12 = 0.5 * (dots(p0, hd, dv) + dots(d, h0, dv))
+        a22 = dots(d, hd, dv)
+        b11 = dots(p0, p0, dv)
+        b12 = dots(p0, d, dv)
+        b22 = dots(d, d, dv)
+        lm = np.array([trial_lambda(a11[s], a12[s], a22[s], b11[s], b12[s], b22[s])
+                       for s in range(len(A))])
+        lam[A] = lm
+        hist_p = [p0, p0 + lm[:, None] * d]
+        hist_h = [h0, h0 + lm[:, None] * hd]
+        moving = lm != 0.0
+        for _ in range(1, opts.m):
+            L = len(hist_p) - 1
+            eps = [dots(p, hh, dv) / dots(p, p, dv) for p, hh in zip(hist_p, hist_h)]
+            R = [hh - e[:, None] * p for p, hh, e in zip(hist_p, hist_h, eps)]
+            ev = [hist_p[L]] + [hist_p[i] - hist_p[L] for i in range(L)]
+            hv = [hist_h[L]] + [hist_h[i] - hist_h[L] for i in range(L)]
+            rv = [R[L]] + [R[i] - R[L] for i in range(L)]
+            n = L + 1
+            Am = np.empty((len(A), n, n))
+            Bm = np.empty((len(A), n, n))
+            for a in range(n):
+                for b in range(a, n):
+                    Am[:, a, b] = Am[:, b, a] = dots(rv[a], rv[b], dv)
+                    Bm[:, a, b] = Bm[:, b, a] = dots(ev[a], ev[b], dv)
+            c = np.zeros((len(A), n))
+            for s in range(len(A)):
+                if moving[s]:
+                    c[s] = diis_coefficients(Am[s], Bm[s])
+                else:
+                    c[s, 0] = 1.0
+            pbar = sum(c[:, a, None] * ev[a] for a in range(n))
+            hbar = sum(c[:, a, None] * hv[a] for a in range(n))
+            rbar = sum(c[:, a, None] * rv[a] for a in range(n))
+            d = filter_precond(g, rbar, nbr, opts.alpha)
+            hd = H.apply(d)
+            hist_p.append(pbar + lm[:, None] * d)
+            hist_h.append(hbar + lm[:, None] * hd)
+        psi = psi.copy()
+        psi[A] = hist_p[-1]
+    psi, _, _ = orthonormalize(psi, dv)
+    return dict(psi=psi, eig=eig, resnorm=res, active=active, lam=lam)
+
+
+def eigensolve(H, psi: np.ndarray, opts: Options, max_steps: int,
+               eref: Optional[np.ndarray] = None, etol: float = 1e-6):
+    """Iterate rmmdiis_step from orthonormalised psi until every residual is
+    below opts.tol (or, with eref, every eigenvalue is within etol)."""
+    psi, _, _ = orthonormalize(psi, H.dv)
+    hist = []
+    for it in range(max_steps):
+        out = rmmdiis_step(H, psi, opts)
+        psi = out["psi"]
+        hist.append((out["eig"].copy(), out["resnorm"].copy()))
+        if eref is not None:
+            if np.max(np.abs(out["eig"] - eref)) < etol:
+                break
+        elif np.all(out["resnorm"] < opts.tol):
+            break
+    return psi, hist

@@ -1,0 +1,105 @@
+"""Pins of the oracle's RMM-DIIS step, filter preconditioner and converged
+eigenvalues (CPU only)."""
+import numpy as np
+import pytest
+import scipy.optimize
+
+import synthetic
+from oracle import grid, hamiltonian, linalg, rmmdiis, stencil
+
+
+def test_filter_symbol_on_plane_waves():
+    n, h = 12, 0.25
+    g = grid.build_grid("periodic", h, n=n)
+    L = n * h
+    for nvec in [(0, 0, 0), (1, 2, 0), (6, 6, 6), (6, 0, 0), (3, 5, 1)]:
+        k = 2 * np.pi * np.array(nvec) / L
+        f = np.cos(g.xyz @ k)
+        got = rmmdiis.filter_precond(g, f)
+        sym = 0.5 + 0.5 / 3 * np.sum(np.cos(k * h))
+        assert np.max(np.abs(got - sym * f)) < 1e-13
+    # the symbol is 1 at k = 0 and 0 at the Nyquist corner
+    f = np.cos(g.xyz @ (np.pi / h * np.ones(3)))
+    assert np.max(np.abs(rmmdiis.filter_precond(g, f))) < 1e-13
+
+
+def test_filter_zero_outside_domain():
+    g = grid.build_grid("box", 0.3, n=4)
+    f = np.ones(g.np)
+    out = rmmdiis.filter_precond(g, f)
+    corner = np.nonzero(np.all(g.inner == 0, axis=1))[0][0]
+    centre = np.nonzero(np.all(g.inner == 1, axis=1))[0][0]
+    assert out[corner] == pytest.approx(0.5 + 0.5 / 6 * 3)
+    assert out[centre] == pytest.approx(1.0)
+
+
+def test_trial_lambda_minimises_rayleigh_quotient():
+    w = synthetic.make_config(2, radius=1.6, h=0.25, nat=2, atom_radius=0.6, rc=1.0)
+    g, _, H = hamiltonian.build_system(w)
+    rng = np.random.default_rng(7)
+    dv = g.dv
+    for _ in range(4):
+        p = rng.uniform(-1, 1, g.np)
+        d = rng.uniform(-1, 1, g.np)
+        hp, hd = H.apply(p), H.apply(d)
+        lam = rmmdiis.trial_lambda(dv * p @ hp, dv * 0.5 * (p @ hd + d @ hp), dv * d @ hd,
+                                   dv * p @ p, dv * p @ d, dv * d @ d)
+        rq = lambda t: ((p + t * d) @ H.apply(p + t * d)) / ((p + t * d) @ (p + t * d))
+        best = scipy.optimize.minimize_scalar(rq, bracket=(lam - 1, lam, lam + 1), tol=1e-12)
+        assert rq(lam) <= best.fun + 1e-10 * abs(best.fun)
+
+
+def test_diis_coefficients_minimise_ratio():
+    rng = np.random.default_rng(8)
+    for n in (2, 3):
+        X = rng.normal(size=(n, 50))
+        Y = rng.normal(size=(n, 50))
+        A, B = X @ X.T, Y @ Y.T
+        c = rmmdiis.diis_coefficients(A, B)
+        assert c[0] == 1.0
+        f = lambda z: (np.r_[1.0, z] @ A @ np.r_[1.0, z]) / (np.r_[1.0, z] @ B @ np.r_[1.0, z])
+        best = scipy.optimize.minimize(f, np.zeros(n - 1), method="Nelder-Mead",
+                                       options=dict(xatol=1e-12, fatol=1e-14, maxiter=20000))
+        assert f(c[1:]) <= best.fun + 1e-9 * best.fun
+    # singular B falls back to keeping the latest iterate
+    c = rmmdiis.diis_coefficients(np.eye(2), np.zeros((2, 2)))
+    assert list(c) == [1.0, 0.0]
+
+
+def test_converged_eigenvalues_harmonic_box():
+    """Lowest four levels of the 32^3 harmonic box (exact discrete values from
+    the separable 1-D problems) from random starts."""
+    w = synthetic.make_config(1, nstates=4)
+    g, _, H = hamiltonian.build_system(w)
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), 4, g.np)
+    psi, hist = rmmdiis.eigensolve(H, psi, rmmdiis.Options(block=4, tol=1e-9), 120)
+    want = np.array([1.4999991750, 2.4999964915, 2.4999964915, 2.4999964915])
+    assert np.max(np.abs(hist[-1][0] - want)) < 1e-9
+    assert np.max(hist[-1][1]) < 1e-9
+
+
+def test_converged_eigenvalues_dense_bruteforce():
+    """Tiny sphere with wells and projectors: the eigensolver reaches the
+    lowest eigenvalues of the assembled dense matrix."""
+    w = synthetic.make_config(2, radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
+    g, _, H = hamiltonian.build_system(w)
+    ev = np.linalg.eigvalsh(H.dense())
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), 4, g.np)
+    psi, hist = rmmdiis.eigensolve(H, psi, rmmdiis.Options(block=4, tol=1e-9), 300)
+    assert np.max(np.abs(hist[-1][0] - ev[:4])) < 1e-10
+
+
+def test_step_keeps_orthonormality_and_block_stop():
+    w = synthetic.make_config(2, radius=2.0, nat=2, atom_radius=0.8)
+    g, _, H = hamiltonian.build_system(w)
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), 8, g.np)
+    psi, _, _ = linalg.orthonormalize(psi, g.dv)
+    out = rmmdiis.rmmdiis_step(H, psi, rmmdiis.Options(block=4))
+    assert np.allclose(g.dv * out["psi"] @ out["psi"].T, np.eye(8), atol=1e-12)
+    assert np.all(np.diff(out["eig"]) >= 0)
+    # with a huge tolerance every block is frozen: the step is RR + ortho only
+    frozen = rmmdiis.rmmdiis_step(H, psi, rmmdiis.Options(block=4, tol=1e9))
+    assert not frozen["active"].any()
+    lam, xi, p2, _ = linalg.rayleigh_ritz(psi, H.apply(psi), g.dv)
+    p2, _, _ = linalg.orthonormalize(p2, g.dv)
+    assert np.allclose(frozen["psi"], p2, atol=1e-10)
