@@ -1,0 +1,181 @@
+/*
+ * rsdft.h - C ABI of the MI355X (gfx950) real-space Kohn-Sham hot path.
+ *
+ * Implements the data-parallel core of Andrade & Aspuru-Guzik, "Real-space
+ * density functional theory on graphical processing units" (arXiv 1306.2953):
+ * applying the Kohn-Sham Hamiltonian to blocks of states on an irregular grid
+ * (Sec. 5), and the orthogonalisation and subspace diagonalisation that the
+ * RMM-DIIS eigensolver wraps around it (Secs. 3 and 6).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns an rs_status; 0 (RS_OK) is success.  On failure
+ *    rs_last_error() gives a message (thread-local, valid until the next
+ *    call on the same thread).  No C++ exception crosses this boundary.
+ *  - Field arrays are caller-owned DEVICE memory on the current HIP device,
+ *    contiguous, 16-byte aligned, in the "block of states" layout of Sec. 4
+ *    (Fig. "memory_layout" (b)): psi[blk][point][B], the B states of a block
+ *    stored contiguously for each grid point, blocks one after another.
+ *    B is a power of two, 1 <= B <= 64 (Sec. 4: block size is chosen at run
+ *    time and restricted to small powers of two).  Points are the grid's
+ *    inner points in index-map order (rs_grid_export); values outside the
+ *    domain are zero (finite systems) or periodic images (periodic box) and
+ *    are never stored.
+ *  - dtype selects the storage type of fields: RS_F64 (double) or RS_F32
+ *    (float).  Small matrices (overlap, subspace Hamiltonian, Cholesky
+ *    factor, eigenvectors, eigenvalues) are always double.
+ *  - Host arrays passed to *_create calls are copied; handles own their
+ *    device tables and scratch, sized at creation, so the field calls never
+ *    allocate device memory.
+ *  - `stream` is a hipStream_t (0 = the null stream).  Field calls only
+ *    enqueue work on it and return without waiting, unless stated.
+ *  - The grid inner product is <f|g> = h^3 sum_p f(p) g(p) (the integral of
+ *    eq. (6) and eqs. (7), (9) replaced by a grid sum).
+ */
+#ifndef RSDFT_H
+#define RSDFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int rs_status;
+#define RS_OK          0
+#define RS_EINVAL      1  /* bad argument (null, size, alignment, B, dtype) */
+#define RS_ENOTPOSDEF  2  /* overlap matrix not positive definite          */
+#define RS_ENONFINITE  3  /* a non-finite value was produced or found      */
+#define RS_EHIP        4  /* HIP runtime failure                           */
+#define RS_ENOMEM      5  /* device or host allocation failure             */
+#define RS_ENOTSUP     6  /* valid but unsupported combination             */
+
+#define RS_F64 0
+#define RS_F32 1
+
+/* Contraction precision of the point-summed products (overlap, subspace
+ * matrix, rotations).  RS_PREC_NATIVE: the storage type, with FP64
+ * accumulation of the split-K partial sums.  RS_PREC_BF16X3: FP32 fields
+ * split as a = a_hi + a_lo (each bfloat16, round to nearest even), products
+ * a_hi b_hi + a_hi b_lo + a_lo b_hi on matrix cores with FP32 accumulation,
+ * partial sums over point chunks added in FP64. */
+#define RS_PREC_NATIVE 0
+#define RS_PREC_BF16X3 1
+
+const char *rs_last_error(void);
+int rs_version(void);
+
+/* ------------------------------------------------------------------ grid
+ * Sec. 2 / Sec. 5.1: a uniform grid of spacing h restricted to a shape, with
+ * points enumerated by small parallelepipedic sub-grids ("bricks",
+ * Fig. "locality" (b)).
+ *
+ * kind  RS_GRID_BOX:      n^3 points, cell-centred (x_i = (i - (n-1)/2) h),
+ *                         zero outside (finite system).
+ *       RS_GRID_PERIODIC: n^3 points, x_i = i h, periodic with L = n h;
+ *                         n must be a multiple of each brick edge.
+ *       RS_GRID_SPHERE:   points (i, j, k) h with i^2 + j^2 + k^2 <= Q, where
+ *                         Q = q^2 if R/h equals an integer q to 1e-9 relative
+ *                         and floor((R/h)^2) otherwise; zero outside.
+ * brick: sub-grid edge lengths (>= 1).  The kernels of this library require
+ *        the default 4 x 4 x 4; other shapes only change the index map.
+ * Ordering: bricks x fastest, then y, then z over the brick lattice (which
+ * starts 4 points before the domain on each side for finite systems);
+ * inside a brick x is fastest.  Inner points come first; "boundary" points
+ * (outside, within 4 steps of an inner point along one axis) are listed
+ * separately by rs_grid_export and are implicit zeros in every kernel.
+ */
+#define RS_GRID_BOX      0
+#define RS_GRID_PERIODIC 1
+#define RS_GRID_SPHERE   2
+
+typedef struct rs_grid rs_grid;
+
+typedef struct {
+    int32_t kind;
+    double  h;         /* spacing (bohr), > 0                      */
+    int32_t n;         /* edge in points (box, periodic)           */
+    double  radius;    /* sphere radius (bohr)                     */
+    int32_t brick[3];  /* sub-grid edges; {0,0,0} selects 4,4,4    */
+    int32_t flags;     /* RS_GRID_HOST_ONLY: build the index map on  */
+                       /* the host only (no device tables; field     */
+                       /* calls on such a grid return RS_EINVAL)     */
+} rs_grid_desc;
+
+#define RS_GRID_HOST_ONLY 1
+
+/* Builds the index map on the host and uploads the brick tables to the
+ * current device (unless RS_GRID_HOST_ONLY).  Errors: RS_EINVAL for a bad
+ * descriptor, RS_EHIP / RS_ENOMEM from the upload. */
+rs_status rs_grid_create(const rs_grid_desc *desc, rs_grid **out);
+void rs_grid_destroy(rs_grid *g);
+
+/* Sizes: inner points, boundary points, numbered bricks (those holding an
+ * inner point), brick-lattice counts nb[3] (x, y, z) and the integer
+ * coordinate lo[3] of the lattice origin.  Any pointer may be NULL. */
+rs_status rs_grid_info(const rs_grid *g, int64_t *np, int64_t *nbnd,
+                       int64_t *nbricks, int32_t nb[3], int32_t lo[3]);
+
+/* Host copies of the index map: integer coordinates of inner [np][3] and
+ * boundary [nbnd][3] points (x, y, z), the brick map [nb2][nb1][nb0] (brick
+ * number or -1), and physical coordinates of inner points [np][3] in bohr.
+ * Any pointer may be NULL. */
+rs_status rs_grid_export(const rs_grid *g, int32_t *inner, int32_t *boundary,
+                         int32_t *brick_map, double *xyz);
+
+/* ------------------------------------------------------- non-local part
+ * Eq. (6), Sec. 5.3, with a diagonal coupling: V_nl = sum_A sum_i
+ * |gamma_A,i> D_A,i <gamma_A,i|, i in {s, p_x, p_y, p_z}, where
+ * gamma_s = N_s exp(-r^2 / 2 sigma^2), gamma_p_a = N_p r_a exp(-r^2/2 sigma^2),
+ * N_s = (pi^1.5 sigma^3)^-1/2, N_p = (pi^1.5 sigma^5 / 2)^-1/2, nonzero for
+ * |r_p - R_A|^2 <= rc^2 (minimum image on periodic grids).  Atoms are split
+ * into colour groups with disjoint spheres (greedy, atom order; Fig. "colors").
+ *
+ * pos [nat][3] (bohr) and D [nat][4] (Ha) are host arrays.  max_states is the
+ * largest nblk*B later passed to the field calls (sizes scratch).  On a
+ * host-only grid the set is built on the host only (export works, field
+ * calls return RS_EINVAL). */
+typedef struct rs_nl rs_nl;
+rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *pos,
+                       const double *D, double rc, double sigma,
+                       int32_t max_states, rs_nl **out);
+void rs_nl_destroy(rs_nl *nl);
+/* Total sphere entries and number of colour groups (either may be NULL). */
+rs_status rs_nl_info(const rs_nl *nl, int64_t *nnz, int32_t *ncolours);
+/* Host copies: sph_ptr [nat+1], sph_idx [nnz] (inner-point indices, ascending
+ * per atom), gamma [nnz][4], colour [nat].  Any pointer may be NULL. */
+rs_status rs_nl_export(const rs_nl *nl, int64_t *sph_ptr, int64_t *sph_idx,
+                       double *gamma, int32_t *colour);
+
+/* ------------------------------------------------------------- H psi
+ * Sec. 5: hpsi = (T + V + V_nl) psi for nblk blocks of B states.
+ *   T: -1/(2h^2) sum_axes sum_{m=1..4} c_m [(psi(p+m e) - psi(p)) +
+ *      (psi(p-m e) - psi(p))], c = (8/5, -1/5, 8/315, -1/560), the 25-point
+ *      star of Sec. 5.1 (equal to the c_0 form since c_0 = -2 sum c_m);
+ *   V: vloc [np] (dtype), Sec. 5.2;
+ *   V_nl: eq. (6) when nl != NULL (projections, then the point-centric sum
+ *      over the atoms whose sphere holds the point; no atomics).
+ * psi [nblk][np][B] and hpsi [nblk][np][B] must not overlap.  Asynchronous.
+ * Errors: RS_EINVAL (B, dtype, pointers, nblk*B > max_states of nl),
+ * RS_ENOTSUP (brick other than 4x4x4). */
+rs_status rs_hpsi_block(const rs_grid *g, const rs_nl *nl, const void *vloc,
+                        const void *psi, void *hpsi, int32_t nblk, int32_t B,
+                        int32_t dtype, void *stream);
+
+/* First part of eq. (6): proj[blk][A][i][s] = h^3 sum_{p in sphere A}
+ * gamma_A,i(p) psi[blk][p][s] (D not applied), FP64 accumulation, stored in
+ * dtype.  Asynchronous. */
+rs_status rs_project_nl(const rs_grid *g, const rs_nl *nl, const void *psi,
+                        void *proj, int32_t nblk, int32_t B, int32_t dtype,
+                        void *stream);
+
+/* Second part of eq. (6): hpsi[blk][p][s] += sum_{A : p in sphere A}
+ * sum_i gamma_A,i(p) D_A,i proj[blk][A][i][s].  Asynchronous. */
+rs_status rs_apply_nl(const rs_grid *g, const rs_nl *nl, const void *proj,
+                      void *hpsi, int32_t nblk, int32_t B, int32_t dtype,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSDFT_H */

@@ -1,0 +1,203 @@
+"""MI355X-native real-space Kohn-Sham hot path (Andrade & Aspuru-Guzik,
+arXiv 1306.2953): H psi on blocks of states over an irregular grid,
+orthogonalisation, subspace diagonalisation and an RMM-DIIS step.
+
+This module is the thin Python binding of librsdft.so: it converts torch
+tensors (device memory and the current HIP stream) into the pointers and
+sizes of the C ABI declared in include/rsdft.h.  No arithmetic of the method
+happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _abi
+from ._abi import (RS_F32, RS_F64, RS_GRID_BOX, RS_GRID_HOST_ONLY, RS_GRID_PERIODIC,
+                   RS_GRID_SPHERE, RS_PREC_BF16X3, RS_PREC_NATIVE, RsError, check, lib)
+
+_KINDS = {"box": RS_GRID_BOX, "periodic": RS_GRID_PERIODIC, "sphere": RS_GRID_SPHERE}
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Grid:
+    """Index map of a uniform grid restricted to a box or sphere (rs_grid)."""
+
+    def __init__(self, kind: str, h: float, n: int = 0, radius: float = 0.0,
+                 brick: Sequence[int] = (4, 4, 4), host_only: bool = False):
+        d = _abi.GridDesc()
+        d.kind = _KINDS[kind]
+        d.h = float(h)
+        d.n = int(n)
+        d.radius = float(radius)
+        for a in range(3):
+            d.brick[a] = int(brick[a])
+        d.flags = RS_GRID_HOST_ONLY if host_only else 0
+        self.kind, self.h, self.n, self.radius = kind, float(h), int(n), float(radius)
+        self.host_only = host_only
+        self._h = ctypes.c_void_p()
+        check(lib().rs_grid_create(ctypes.byref(d), ctypes.byref(self._h)))
+        np_, nb_, nbr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        nb = (ctypes.c_int32 * 3)()
+        lo = (ctypes.c_int32 * 3)()
+        check(lib().rs_grid_info(self._h, ctypes.byref(np_), ctypes.byref(nb_),
+                                 ctypes.byref(nbr), nb, lo))
+        self.np, self.nbnd, self.nbricks = np_.value, nb_.value, nbr.value
+        self.nb = tuple(nb)
+        self.lo = tuple(lo)
+
+    @classmethod
+    def for_workload(cls, w, host_only: bool = False) -> "Grid":
+        if w.grid_kind == "sphere":
+            return cls("sphere", w.h, radius=w.radius, host_only=host_only)
+        return cls(w.grid_kind, w.h, n=w.n, host_only=host_only)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def dv(self) -> float:
+        return self.h ** 3
+
+    def export(self):
+        inner = np.empty((self.np, 3), dtype=np.int32)
+        bnd = np.empty((max(self.nbnd, 1), 3), dtype=np.int32)
+        bmap = np.empty((self.nb[2], self.nb[1], self.nb[0]), dtype=np.int32)
+        xyz = np.empty((self.np, 3), dtype=np.float64)
+        check(lib().rs_grid_export(self._h, _ptr(inner), _ptr(bnd), _ptr(bmap), _ptr(xyz)))
+        return dict(inner=inner, boundary=bnd[: self.nbnd], brick_map=bmap, xyz=xyz)
+
+    def xyz(self) -> np.ndarray:
+        xyz = np.empty((self.np, 3), dtype=np.float64)
+        check(lib().rs_grid_export(self._h, None, None, None, _ptr(xyz)))
+        return xyz
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_grid_destroy(h)
+            self._h = None
+
+
+class NonLocal:
+    """Kleinman-Bylander projector set (rs_nl)."""
+
+    def __init__(self, grid: Grid, pos: np.ndarray, D: np.ndarray, rc: float,
+                 sigma: float, max_states: int):
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1, 4)
+        self.grid = grid
+        self.nat = pos.shape[0]
+        self._h = ctypes.c_void_p()
+        check(lib().rs_nl_create(grid.handle, self.nat, _ptr(pos), _ptr(D), float(rc),
+                                 float(sigma), int(max_states), ctypes.byref(self._h)))
+        nnz, ncol = ctypes.c_int64(), ctypes.c_int32()
+        check(lib().rs_nl_info(self._h, ctypes.byref(nnz), ctypes.byref(ncol)))
+        self.nnz, self.ncolours = nnz.value, ncol.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        ptr = np.empty(self.nat + 1, dtype=np.int64)
+        idx = np.empty(max(self.nnz, 1), dtype=np.int64)
+        gam = np.empty((max(self.nnz, 1), 4), dtype=np.float64)
+        col = np.empty(max(self.nat, 1), dtype=np.int32)
+        check(lib().rs_nl_export(self._h, _ptr(ptr), _ptr(idx), _ptr(gam), _ptr(col)))
+        return dict(sph_ptr=ptr, sph_idx=idx[: self.nnz], gamma=gam[: self.nnz],
+                    colour=col[: self.nat])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_nl_destroy(h)
+            self._h = None
+
+
+# ------------------------------------------------------------ torch glue
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return RS_F64
+    if t.dtype == torch.float32:
+        return RS_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _blocks(psi, grid: Grid):
+    if psi.dim() != 3 or psi.shape[1] != grid.np:
+        raise ValueError(f"psi must be [nblk, np={grid.np}, B], got {tuple(psi.shape)}")
+    return psi.shape[0], psi.shape[2]
+
+
+def hpsi_block(grid: Grid, nl: Optional[NonLocal], vloc, psi, hpsi, stream=None):
+    """hpsi = (T + V + V_nl) psi for psi [nblk, np, B] (rs_hpsi_block)."""
+    nblk, B = _blocks(psi, grid)
+    if hpsi.shape != psi.shape or hpsi.dtype != psi.dtype or vloc.dtype != psi.dtype:
+        raise ValueError("hpsi/vloc must match psi in shape/dtype")
+    check(lib().rs_hpsi_block(grid.handle, nl.handle if nl is not None else None,
+                              _dev(vloc, "vloc"), _dev(psi, "psi"), _dev(hpsi, "hpsi"),
+                              nblk, B, _dtype_code(psi), _stream(stream)))
+    return hpsi
+
+
+def project_nl(grid: Grid, nl: NonLocal, psi, proj, stream=None):
+    """proj [nblk, nat, 4, B] = h^3 <gamma_A,i|psi> (rs_project_nl)."""
+    nblk, B = _blocks(psi, grid)
+    if tuple(proj.shape) != (nblk, nl.nat, 4, B) or proj.dtype != psi.dtype:
+        raise ValueError("proj must be [nblk, nat, 4, B] of psi's dtype")
+    check(lib().rs_project_nl(grid.handle, nl.handle, _dev(psi, "psi"), _dev(proj, "proj"),
+                              nblk, B, _dtype_code(psi), _stream(stream)))
+    return proj
+
+
+def apply_nl(grid: Grid, nl: NonLocal, proj, hpsi, stream=None):
+    """hpsi += sum gamma D proj (rs_apply_nl)."""
+    nblk, B = _blocks(hpsi, grid)
+    if tuple(proj.shape) != (nblk, nl.nat, 4, B) or proj.dtype != hpsi.dtype:
+        raise ValueError("proj must be [nblk, nat, 4, B] of hpsi's dtype")
+    check(lib().rs_apply_nl(grid.handle, nl.handle, _dev(proj, "proj"), _dev(hpsi, "hpsi"),
+                            nblk, B, _dtype_code(hpsi), _stream(stream)))
+    return hpsi
+
+
+def to_blocks(states: np.ndarray, B: int) -> np.ndarray:
+    """State-major [N, np] -> block layout [N/B, np, B] (host-side reshuffle)."""
+    N, npts = states.shape
+    if N % B:
+        raise ValueError("N must be a multiple of B")
+    return np.ascontiguousarray(states.reshape(N // B, B, npts).transpose(0, 2, 1))
+
+
+def from_blocks(blocks: np.ndarray) -> np.ndarray:
+    """Block layout [nblk, np, B] -> state-major [nblk*B, np]."""
+    nblk, npts, B = blocks.shape
+    return np.ascontiguousarray(blocks.transpose(0, 2, 1).reshape(nblk * B, npts))

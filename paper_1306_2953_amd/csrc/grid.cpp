@@ -1,0 +1,207 @@
+// Host construction of the grid index map (Sec. 2, Sec. 5.1) and of the
+// per-brick tables the stencil kernels read.  Built with -ffp-contract=off:
+// membership is integer-only and coordinates are (i - c) * h rounded as
+// written.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr int kReach = 4;   // stencil half-width (25-point star)
+
+struct SphereRule { int64_t q, Q; };
+
+SphereRule sphere_rule(double radius, double h) {
+    const double x = radius / h;
+    const double qr = std::nearbyint(x);
+    const int64_t q = (int64_t)qr;
+    if (std::fabs(x - qr) <= 1e-9 * std::max<double>((double)q, 1.0)) return {q, q * q};
+    return {(int64_t)std::floor(x), (int64_t)std::floor(x * x)};
+}
+
+}  // namespace
+
+extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
+    using namespace rs;
+    if (!d || !out) return fail(RS_EINVAL, "rs_grid_create: null argument");
+    *out = nullptr;
+    if (!(d->h > 0) || !std::isfinite(d->h)) return fail(RS_EINVAL, "grid spacing must be > 0");
+    int br[3] = {d->brick[0], d->brick[1], d->brick[2]};
+    if (br[0] == 0 && br[1] == 0 && br[2] == 0) br[0] = br[1] = br[2] = 4;
+    for (int a = 0; a < 3; ++a)
+        if (br[a] < 1 || br[a] > 4096) return fail(RS_EINVAL, "brick edges must be >= 1");
+
+    auto g = new (std::nothrow) rs_grid();
+    if (!g) return fail(RS_ENOMEM, "host allocation failed");
+    g->kind = d->kind;
+    g->h = d->h;
+    g->n = d->n;
+    g->radius = d->radius;
+    g->host_only = (d->flags & RS_GRID_HOST_ONLY) != 0;
+    for (int a = 0; a < 3; ++a) g->brick[a] = br[a];
+
+    int64_t lo_in = 0, ext = 0, pad = 0, Q = 0;
+    if (d->kind == RS_GRID_SPHERE) {
+        if (!(d->radius > 0)) { delete g; return fail(RS_EINVAL, "sphere radius must be > 0"); }
+        SphereRule r = sphere_rule(d->radius, d->h);
+        if (r.q > 20000) { delete g; return fail(RS_EINVAL, "sphere too large"); }
+        lo_in = -r.q; ext = 2 * r.q + 1; pad = kReach; Q = r.Q;
+        g->centre = 0.0;
+    } else if (d->kind == RS_GRID_BOX || d->kind == RS_GRID_PERIODIC) {
+        if (d->n < 1 || d->n > 20000) { delete g; return fail(RS_EINVAL, "box edge out of range"); }
+        lo_in = 0; ext = d->n;
+        pad = d->kind == RS_GRID_BOX ? kReach : 0;
+        g->centre = d->kind == RS_GRID_BOX ? 0.5 * (double)(d->n - 1) : 0.0;
+        if (d->kind == RS_GRID_PERIODIC)
+            for (int a = 0; a < 3; ++a)
+                if (d->n % br[a]) { delete g; return fail(RS_EINVAL, "periodic edge must be a multiple of the brick"); }
+    } else {
+        delete g;
+        return fail(RS_EINVAL, "unknown grid kind");
+    }
+    for (int a = 0; a < 3; ++a) {
+        g->lo[a] = lo_in - pad;
+        g->L[a] = ext + 2 * pad;
+        g->nb[a] = (g->L[a] + br[a] - 1) / br[a];
+    }
+    const int64_t L0 = g->L[0], L1 = g->L[1], L2 = g->L[2];
+    const int64_t ntot = L0 * L1 * L2;
+    std::vector<uint8_t> inside(ntot, 0);
+    for (int64_t k = 0; k < L2; ++k)
+        for (int64_t j = 0; j < L1; ++j)
+            for (int64_t i = 0; i < L0; ++i) {
+                const int64_t x = i + g->lo[0], y = j + g->lo[1], z = k + g->lo[2];
+                bool in;
+                if (d->kind == RS_GRID_SPHERE) in = x * x + y * y + z * z <= Q;
+                else in = x >= 0 && x < ext && y >= 0 && y < ext && z >= 0 && z < ext;
+                inside[(k * L1 + j) * L0 + i] = in;
+            }
+    auto is_in = [&](int64_t i, int64_t j, int64_t k) -> bool {
+        if (i < 0 || j < 0 || k < 0 || i >= L0 || j >= L1 || k >= L2) return false;
+        return inside[(k * L1 + j) * L0 + i];
+    };
+
+    g->lookup.assign(ntot, -1);
+    const int64_t nbx = g->nb[0], nby = g->nb[1], nbz = g->nb[2];
+    g->brick_map.assign(nbx * nby * nbz, -1);
+    int64_t nbricks = 0;
+    std::vector<int64_t> brick_first;   // first inner index per numbered brick
+    // pass 1: inner points in brick order
+    for (int64_t bz = 0; bz < nbz; ++bz)
+        for (int64_t by = 0; by < nby; ++by)
+            for (int64_t bx = 0; bx < nbx; ++bx) {
+                const int64_t before = g->np;
+                for (int sz = 0; sz < br[2]; ++sz)
+                    for (int sy = 0; sy < br[1]; ++sy)
+                        for (int sx = 0; sx < br[0]; ++sx) {
+                            const int64_t i = bx * br[0] + sx, j = by * br[1] + sy, k = bz * br[2] + sz;
+                            if (!is_in(i, j, k)) continue;
+                            g->lookup[(k * L1 + j) * L0 + i] = g->np++;
+                            g->inner.push_back((int32_t)(i + g->lo[0]));
+                            g->inner.push_back((int32_t)(j + g->lo[1]));
+                            g->inner.push_back((int32_t)(k + g->lo[2]));
+                        }
+                if (g->np > before) {
+                    g->brick_map[(bz * nby + by) * nbx + bx] = (int32_t)nbricks++;
+                    brick_first.push_back(before);
+                }
+            }
+    // pass 2: boundary points (finite systems), same order
+    if (d->kind != RS_GRID_PERIODIC) {
+        for (int64_t bz = 0; bz < nbz; ++bz)
+            for (int64_t by = 0; by < nby; ++by)
+                for (int64_t bx = 0; bx < nbx; ++bx)
+                    for (int sz = 0; sz < br[2]; ++sz)
+                        for (int sy = 0; sy < br[1]; ++sy)
+                            for (int sx = 0; sx < br[0]; ++sx) {
+                                const int64_t i = bx * br[0] + sx, j = by * br[1] + sy, k = bz * br[2] + sz;
+                                if (i >= L0 || j >= L1 || k >= L2 || is_in(i, j, k)) continue;
+                                bool hit = false;
+                                for (int m = 1; m <= kReach && !hit; ++m)
+                                    hit = is_in(i + m, j, k) || is_in(i - m, j, k) ||
+                                          is_in(i, j + m, k) || is_in(i, j - m, k) ||
+                                          is_in(i, j, k + m) || is_in(i, j, k - m);
+                                if (!hit) continue;
+                                g->nbnd++;
+                                g->boundary.push_back((int32_t)(i + g->lo[0]));
+                                g->boundary.push_back((int32_t)(j + g->lo[1]));
+                                g->boundary.push_back((int32_t)(k + g->lo[2]));
+                            }
+    }
+    g->nbricks = nbricks;
+
+    // per-brick kernel tables (4x4x4 only)
+    g->kernels_ok = br[0] == 4 && br[1] == 4 && br[2] == 4;
+    if (g->kernels_ok) {
+        if (g->np * 64 >= ((int64_t)1 << 31)) {
+            // offsets inside one block are 32-bit in the kernels
+            g->kernels_ok = false;
+        }
+    }
+    if (g->kernels_ok) {
+        g->bricks_host.resize(nbricks);
+        for (int64_t bz = 0; bz < nbz; ++bz)
+            for (int64_t by = 0; by < nby; ++by)
+                for (int64_t bx = 0; bx < nbx; ++bx) {
+                    const int32_t b = g->brick_map[(bz * nby + by) * nbx + bx];
+                    if (b < 0) continue;
+                    BrickRec &r = g->bricks_host[b];
+                    r.mask = 0;
+                    r.start = (int32_t)brick_first[b];
+                    r.reserved = 0;
+                    for (int s = 0; s < 64; ++s) {
+                        const int64_t i = bx * 4 + (s & 3), j = by * 4 + ((s >> 2) & 3), k = bz * 4 + (s >> 4);
+                        if (is_in(i, j, k)) r.mask |= (uint64_t)1 << s;
+                    }
+                    const int64_t c[3] = {bx, by, bz};
+                    for (int a = 0; a < 3; ++a)
+                        for (int sgn = 0; sgn < 2; ++sgn) {
+                            int64_t cc[3] = {c[0], c[1], c[2]};
+                            cc[a] += sgn ? 1 : -1;
+                            int32_t nbid = -1;
+                            if (d->kind == RS_GRID_PERIODIC) {
+                                cc[a] = (cc[a] + g->nb[a]) % g->nb[a];
+                                nbid = g->brick_map[(cc[2] * nby + cc[1]) * nbx + cc[0]];
+                            } else if (cc[a] >= 0 && cc[a] < g->nb[a]) {
+                                nbid = g->brick_map[(cc[2] * nby + cc[1]) * nbx + cc[0]];
+                            }
+                            r.nbr[a * 2 + sgn] = nbid;
+                        }
+                }
+        if (!g->host_only) {
+            rs_status st = g->bricks.upload(g->bricks_host);
+            if (st) { delete g; return st; }
+        }
+    }
+    *out = g;
+    return RS_OK;
+}
+
+extern "C" void rs_grid_destroy(rs_grid *g) { delete g; }
+
+extern "C" rs_status rs_grid_info(const rs_grid *g, int64_t *np, int64_t *nbnd,
+                                  int64_t *nbricks, int32_t nb[3], int32_t lo[3]) {
+    if (!g) return rs::fail(RS_EINVAL, "rs_grid_info: null grid");
+    if (np) *np = g->np;
+    if (nbnd) *nbnd = g->nbnd;
+    if (nbricks) *nbricks = g->nbricks;
+    for (int a = 0; a < 3; ++a) {
+        if (nb) nb[a] = (int32_t)g->nb[a];
+        if (lo) lo[a] = (int32_t)g->lo[a];
+    }
+    return RS_OK;
+}
+
+extern "C" rs_status rs_grid_export(const rs_grid *g, int32_t *inner, int32_t *boundary,
+                                    int32_t *brick_map, double *xyz) {
+    if (!g) return rs::fail(RS_EINVAL, "rs_grid_export: null grid");
+    if (inner && g->np) std::memcpy(inner, g->inner.data(), g->inner.size() * sizeof(int32_t));
+    if (boundary && g->nbnd) std::memcpy(boundary, g->boundary.data(), g->boundary.size() * sizeof(int32_t));
+    if (brick_map) std::memcpy(brick_map, g->brick_map.data(), g->brick_map.size() * sizeof(int32_t));
+    if (xyz)
+        for (int64_t p = 0; p < 3 * g->np; ++p) xyz[p] = ((double)g->inner[p] - g->centre) * g->h;
+    return RS_OK;
+}

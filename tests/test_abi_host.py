@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol the header declares, and its host-built index map and projector sets
+match the oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import grid as ogrid
+from oracle import kb as okb
+
+rsd = pytest.importorskip("paper_1306_2953_amd")
+from paper_1306_2953_amd import _abi  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "rsdft.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    syms = header_symbols()
+    assert len(syms) >= 10
+    for name in syms:
+        assert hasattr(L, name), name
+    assert sorted(_abi.SIGNATURES) == syms
+    assert L.rs_version() >= 1
+
+
+def test_bad_arguments_are_reported():
+    with pytest.raises(_abi.RsError) as e:
+        rsd.Grid("sphere", -0.2, radius=1.0, host_only=True)
+    assert e.value.code == _abi.RS_EINVAL
+    with pytest.raises(_abi.RsError):
+        rsd.Grid("periodic", 0.25, n=10, host_only=True)   # not a multiple of 4
+
+
+GRIDS = [
+    dict(kind="sphere", h=0.2, radius=12.0),
+    dict(kind="sphere", h=0.2, radius=2.0),
+    dict(kind="sphere", h=0.5, radius=2.6, brick=(2, 3, 4)),
+    dict(kind="sphere", h=0.3, radius=1.05),
+    dict(kind="box", h=0.3, n=32),
+    dict(kind="box", h=0.3, n=6, brick=(4, 4, 4)),
+    dict(kind="periodic", h=0.25, n=16),
+    dict(kind="sphere", h=0.2, radius=3.0, brick=(64, 64, 64)),   # standard order
+]
+
+
+@pytest.mark.parametrize("args", GRIDS, ids=lambda a: "-".join(str(v) for v in a.values()))
+def test_index_map_bit_exact(args):
+    args = dict(args)
+    brick = args.pop("brick", (4, 4, 4))
+    og = ogrid.build_grid(args["kind"], args["h"], n=args.get("n", 0),
+                          radius=args.get("radius", 0.0), brick=brick)
+    g = rsd.Grid(args["kind"], args["h"], n=args.get("n", 0), radius=args.get("radius", 0.0),
+                 brick=brick, host_only=True)
+    assert g.np == og.np and g.nbnd == og.nbnd
+    ex = g.export()
+    assert np.array_equal(ex["inner"], og.inner)
+    assert np.array_equal(ex["boundary"], og.boundary.reshape(-1, 3))
+    assert np.array_equal(ex["brick_map"], og.brick_map)
+    assert np.array_equal(ex["xyz"], og.xyz)          # same rounding of (i - c) h
+    assert tuple(g.lo) == tuple(og.lo)
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(idx=2, radius=4.0, nat=5, atom_radius=2.5),
+    dict(idx=2),
+    dict(idx=4, n=24, nat=6),
+    dict(idx=5, radius=9.0, nat=60, atom_radius=6.7, rc=1.2),
+])
+def test_projector_sets_match_oracle(cfg):
+    idx = cfg.pop("idx")
+    w = synthetic.make_config(idx, **cfg)
+    og = ogrid.grid_for(w)
+    atoms = synthetic.draw_atoms(w)
+    ops = okb.build_projectors(og, atoms.pos, atoms.D, w.rc, w.sigma)
+    g = rsd.Grid.for_workload(w, host_only=True)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=64)
+    ex = nl.export()
+    lens = np.diff(ex["sph_ptr"])
+    assert list(lens) == [len(i) for i in ops.idx]
+    assert np.array_equal(ex["sph_idx"], np.concatenate(ops.idx))
+    gam = np.concatenate(ops.gamma)
+    assert np.max(np.abs(ex["gamma"] - gam)) <= 1e-14 * np.max(np.abs(gam))
+    assert np.array_equal(ex["colour"], ops.colour)

@@ -1,0 +1,147 @@
+"""GPU parity of H psi, the projections and the scatter against the FP64
+oracle, through the C ABI.  Tolerances: FP64 1e-12 relative, FP32 1e-5
+relative (max-norm over all outputs, relative to the largest output)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import hamiltonian, kb, stencil
+
+torch = pytest.importorskip("torch")
+import paper_1306_2953_amd as rsd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+
+
+def _system(w, max_states=256):
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    assert g.np == og.np
+    nl = None
+    if atoms is not None:
+        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=max_states)
+    return og, H, g, nl
+
+
+def _states(w, N, npts, dtype):
+    rng = synthetic.rng_after_atoms(w)
+    return synthetic.draw_states(rng, N, npts).astype(dtype)
+
+
+def _gpu_hpsi(g, nl, v, psi_sm, B, dtype):
+    blk = rsd.to_blocks(psi_sm, B)
+    tp = torch.from_numpy(blk).to(DEV)
+    th = torch.empty_like(tp)
+    tv = torch.from_numpy(np.ascontiguousarray(v.astype(dtype))).to(DEV)
+    rsd.hpsi_block(g, nl, tv, tp, th)
+    torch.cuda.synchronize()
+    return rsd.from_blocks(th.cpu().numpy())
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+SMALL = synthetic.make_config(2, radius=3.0, nat=5, atom_radius=2.0)
+
+
+@pytest.mark.parametrize("B", [1, 2, 4, 8, 16, 32, 64])
+def test_hpsi_fp64_sphere_all_block_sizes(B):
+    og, H, g, nl = _system(SMALL)
+    psi = _states(SMALL, 2 * B, og.np, np.float64)
+    got = _gpu_hpsi(g, nl, H.vloc, psi, B, np.float64)
+    assert _relerr(got, H.apply(psi)) < 1e-12
+
+
+@pytest.mark.parametrize("B", [1, 8, 32, 64])
+def test_hpsi_fp32_sphere(B):
+    og, H, g, nl = _system(SMALL)
+    psi = _states(SMALL, 2 * B, og.np, np.float32)
+    v32 = H.vloc.astype(np.float32)
+    Hq = hamiltonian.Hamiltonian(og, v32.astype(np.float64), H.proj)
+    want = Hq.apply(psi.astype(np.float64))
+    got = _gpu_hpsi(g, nl, v32, psi, B, np.float32)
+    assert _relerr(got, want) < 1e-5
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-6
+
+
+def test_hpsi_box_harmonic_and_periodic():
+    w = synthetic.CONFIGS[1]
+    og, H, g, nl = _system(w)
+    psi = _states(w, 8, og.np, np.float64)
+    got = _gpu_hpsi(g, nl, H.vloc, psi, 8, np.float64)
+    assert _relerr(got, H.apply(psi)) < 1e-12
+    wp = synthetic.make_config(4, n=24, nat=4)
+    og, H, g, nl = _system(wp)
+    psi = _states(wp, 64, og.np, np.float64)
+    got = _gpu_hpsi(g, nl, H.vloc, psi, 32, np.float64)
+    assert _relerr(got, H.apply(psi)) < 1e-12
+
+
+def test_overlapping_spheres_no_race():
+    w = synthetic.make_config(2, radius=2.4, nat=8, atom_radius=0.8, rc=1.5)
+    og, H, g, nl = _system(w)
+    assert nl.ncolours >= 3
+    psi = _states(w, 32, og.np, np.float64)
+    a = _gpu_hpsi(g, nl, H.vloc, psi, 32, np.float64)
+    b = _gpu_hpsi(g, nl, H.vloc, psi, 32, np.float64)
+    assert np.array_equal(a, b)                      # bitwise repeatable
+    assert _relerr(a, H.apply(psi)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+def test_project_and_apply_nl(dtype, tol):
+    og, H, g, nl = _system(SMALL)
+    B, nblk = 16, 3
+    psi = _states(SMALL, nblk * B, og.np, dtype)
+    P = kb.project(H.proj, psi.astype(np.float64))               # [N, nat, 4]
+    tp = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
+    proj = torch.empty((nblk, nl.nat, 4, B), dtype=tp.dtype, device=DEV)
+    rsd.project_nl(g, nl, tp, proj)
+    got = proj.cpu().numpy().transpose(0, 3, 1, 2).reshape(nblk * B, nl.nat, 4)
+    assert _relerr(got, P) < tol
+    # scatter on top of an arbitrary field
+    base = _states(SMALL, nblk * B, og.np, dtype)
+    th = torch.from_numpy(rsd.to_blocks(base, B)).to(DEV)
+    rsd.apply_nl(g, nl, proj, th)
+    torch.cuda.synchronize()
+    want = base.astype(np.float64) + kb.apply_projections(H.proj, got.astype(np.float64), og.np)
+    assert _relerr(rsd.from_blocks(th.cpu().numpy()), want) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+def test_full_size_sphere_sampled(dtype, tol):
+    """Config-2 grid (0.9M points, 16 atoms), all 128 states in blocks of 32,
+    checked at sampled points computed one by one by the oracle."""
+    w = synthetic.CONFIGS[2]
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=128)
+    psi = _states(w, 128, og.np, dtype)
+    v = H.vloc.astype(dtype)
+    got = _gpu_hpsi(g, nl, v, psi, 32, dtype)
+    x64 = psi.astype(np.float64)
+    rng = np.random.default_rng(11)
+    pts = rng.choice(og.np, 300, replace=False)
+    sph = np.concatenate(H.proj.idx)
+    pts = np.unique(np.concatenate([pts, rng.choice(sph, 200, replace=False)]))
+    want = stencil.apply_local_at(og, v.astype(np.float64), x64, pts)
+    P = kb.project(H.proj, x64)
+    want += kb.apply_projections(H.proj, P, og.np)[:, pts]
+    assert _relerr(got[:, pts], want) < tol
+
+
+def test_bad_block_size_rejected():
+    og, H, g, nl = _system(SMALL)
+    t = torch.zeros((1, og.np, 3), dtype=torch.float64, device=DEV)
+    v = torch.zeros(og.np, dtype=torch.float64, device=DEV)
+    with pytest.raises(rsd.RsError) as e:
+        rsd.hpsi_block(g, nl, v, t, torch.empty_like(t))
+    assert e.value.code == rsd._abi.RS_EINVAL
