@@ -56,9 +56,12 @@ typedef int rs_status;
 /* Contraction precision of the point-summed products (overlap, subspace
  * matrix, rotations).  RS_PREC_NATIVE: the storage type, with FP64
  * accumulation of the split-K partial sums.  RS_PREC_BF16X3: FP32 fields
- * split as a = a_hi + a_lo (each bfloat16, round to nearest even), products
- * a_hi b_hi + a_hi b_lo + a_lo b_hi on matrix cores with FP32 accumulation,
- * partial sums over point chunks added in FP64. */
+ * split as a = a_hi + a_lo (each bfloat16, round to nearest even); products
+ * on matrix cores with FP32 accumulation.  Overlaps: a_hi b_hi + a_hi b_lo +
+ * a_lo b_hi + a_lo b_lo (the last keeps norms unbiased), partial sums over
+ * chunks of <= 4096 points added in FP64.  Rotations: the FP64 matrix is
+ * split in three bfloat16 terms x_0 + x_1 + x_2 and multiplied by a_hi and
+ * a_lo (5 products), so no common scale error reaches a whole state. */
 #define RS_PREC_NATIVE 0
 #define RS_PREC_BF16X3 1
 
@@ -174,6 +177,55 @@ rs_status rs_project_nl(const rs_grid *g, const rs_nl *nl, const void *psi,
 rs_status rs_apply_nl(const rs_grid *g, const rs_nl *nl, const void *proj,
                       void *hpsi, int32_t nblk, int32_t B, int32_t dtype,
                       void *stream);
+
+/* -------------------------------------------- orthogonalisation, Sec. 6
+ * A context holds the workspaces of the point-summed contractions and the
+ * small FP64 matrices for up to max_states (<= 256) states of one grid.
+ * Field calls on one context must not overlap in time (shared scratch). */
+typedef struct rs_ctx rs_ctx;
+rs_status rs_ctx_create(const rs_grid *g, int32_t max_states, rs_ctx **out);
+void rs_ctx_destroy(rs_ctx *c);
+
+/* Eq. (7) generalised: S[j][k] = h^3 sum_p X[p][j] Y[p][k] for N = nblk*B
+ * states stored in the block layout; S is DEVICE double [N][N].  When x == y
+ * only the upper 16x16 blocks are formed (symmetric rank-k product) and
+ * mirrored.  Per-chunk (<= 4096 points) partial sums are added in FP64 in a
+ * fixed order (bitwise repeatable).  prec must be RS_PREC_NATIVE for RS_F64
+ * and RS_PREC_BF16X3 for RS_F32 (else RS_ENOTSUP).  Asynchronous. */
+rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t nblk,
+                     int32_t B, int32_t dtype, int32_t prec, void *stream);
+
+/* psi <- psi X in place (eqs. (8) and (10): new state c = sum_n X[n][c] old
+ * state n); X is DEVICE double [N][N].  Asynchronous. */
+rs_status rs_rotate(rs_ctx *c, void *psi, const double *X, int32_t nblk, int32_t B,
+                    int32_t dtype, int32_t prec, void *stream);
+
+/* S = U^T U (Sec. 6), U upper triangular with positive diagonal, all DEVICE
+ * double [N][N]; *info (DEVICE int) = 0 or the 1-based column whose pivot is
+ * not positive (LAPACK potrf convention).  Asynchronous. */
+rs_status rs_cholesky(rs_ctx *c, const double *S, double *U, int32_t N, int32_t *info,
+                      void *stream);
+
+/* Symmetric eigenproblem A V = V diag(evals) by cyclic Jacobi (FP64, DEVICE
+ * arrays; A [N][N] is destroyed).  Eigenvalues ascending; column j of V is
+ * eigenvector j with its largest-magnitude component positive.
+ * Asynchronous. */
+rs_status rs_eigh(rs_ctx *c, double *A, double *V, double *evals, int32_t N, void *stream);
+
+/* Sec. 6, eqs. (7)-(8): S = <psi|psi>, S = U^T U, psi <- psi U^-1 (so the new
+ * states are orthonormal and state j spans the first j old states).  S_out
+ * (DEVICE double [N][N]) may be NULL.  Synchronises the stream to read the
+ * Cholesky status: on a non-positive pivot returns RS_ENOTPOSDEF with *info
+ * (HOST int, may be NULL) the 1-based column, and leaves psi unchanged. */
+rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk, int32_t B,
+                                  int32_t dtype, int32_t prec, double *S_out, int32_t *info,
+                                  void *stream);
+
+/* Sec. 6, eqs. (9)-(10): h = (M + M^T)/2, M = <psi|hpsi>; h = V diag(eig) V^T;
+ * psi <- psi V and hpsi <- hpsi V in place; eig is DEVICE double [N],
+ * ascending.  Asynchronous. */
+rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_t nblk,
+                           int32_t B, int32_t dtype, int32_t prec, void *stream);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,9 @@ Sec. 6.  States are state-major arrays psi[k, p]; the grid inner product is
                  so Psibar = Psi U^-1, classical Gram-Schmidt order)
   subspace       eq. (9): h_jk = <phi_j|H|phi_k>, symmetrised
   rayleigh_ritz  diagonalise h (ascending eigenvalues) and rotate, eq. (10):
-                 phibar_k = sum_j xi_jk phi_j (applied to H psi as well)
+                 phibar_k = sum_j xi_jk phi_j (applied to H psi as well); each
+                 eigenvector's largest-magnitude component is made positive
+                 (the sign is otherwise arbitrary)
 """
 from __future__ import annotations
 
@@ -66,4 +68,11 @@ def rayleigh_ritz(psi: np.ndarray, hpsi: np.ndarray, dv: float):
     """Returns (eigenvalues ascending, xi, rotated psi, rotated H psi)."""
     hm = subspace(psi, hpsi, dv)
     lam, xi = np.linalg.eigh(hm)
+    xi = xi * fix_signs(xi)
     return lam, xi, xi.T @ psi, xi.T @ hpsi
+
+
+def fix_signs(V: np.ndarray) -> np.ndarray:
+    """+1/-1 per column so that each column's largest-|.| entry is positive."""
+    arg = np.argmax(np.abs(V), axis=0)
+    return np.where(V[arg, np.arange(V.shape[1])] < 0, -1.0, 1.0)

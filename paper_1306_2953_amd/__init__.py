@@ -189,6 +189,91 @@ def apply_nl(grid: Grid, nl: NonLocal, proj, hpsi, stream=None):
     return hpsi
 
 
+class Context:
+    """Workspaces of the orthogonalisation / subspace stage (rs_ctx)."""
+
+    def __init__(self, grid: Grid, max_states: int):
+        self.grid = grid
+        self.max_states = max_states
+        self._h = ctypes.c_void_p()
+        check(lib().rs_ctx_create(grid.handle, int(max_states), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_ctx_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def _prec(t, prec):
+        if prec is not None:
+            return prec
+        return RS_PREC_NATIVE if _dtype_code(t) == RS_F64 else RS_PREC_BF16X3
+
+    def overlap(self, x, y, S=None, prec=None, stream=None):
+        """S [N, N] (float64) = h^3 X^T Y (rs_overlap)."""
+        nblk, B = _blocks(x, self.grid)
+        torch = _torch()
+        if S is None:
+            S = torch.empty((nblk * B, nblk * B), dtype=torch.float64, device=x.device)
+        check(lib().rs_overlap(self._h, _dev(x, "x"), _dev(y, "y"), _dev(S, "S"), nblk, B,
+                               _dtype_code(x), self._prec(x, prec), _stream(stream)))
+        return S
+
+    def rotate(self, psi, X, prec=None, stream=None):
+        """psi <- psi X in place (rs_rotate)."""
+        nblk, B = _blocks(psi, self.grid)
+        check(lib().rs_rotate(self._h, _dev(psi, "psi"), _dev(X, "X"), nblk, B,
+                              _dtype_code(psi), self._prec(psi, prec), _stream(stream)))
+        return psi
+
+    def cholesky(self, S, stream=None):
+        """(U, info) with S = U^T U (rs_cholesky); info is a device int32."""
+        torch = _torch()
+        N = S.shape[0]
+        U = torch.empty_like(S)
+        info = torch.zeros(1, dtype=torch.int32, device=S.device)
+        check(lib().rs_cholesky(self._h, _dev(S, "S"), _dev(U, "U"), N, _dev(info, "info"),
+                                _stream(stream)))
+        return U, info
+
+    def eigh(self, A, stream=None):
+        """(evals, V) of symmetric A (rs_eigh); A is copied, not destroyed."""
+        torch = _torch()
+        N = A.shape[0]
+        W = A.clone()
+        V = torch.empty_like(A)
+        ev = torch.empty(N, dtype=torch.float64, device=A.device)
+        check(lib().rs_eigh(self._h, _dev(W, "A"), _dev(V, "V"), _dev(ev, "evals"), N,
+                            _stream(stream)))
+        return ev, V
+
+    def orthonormalize(self, psi, S_out=None, prec=None, stream=None):
+        """psi <- psi U^-1 in place (rs_orthonormalize_block); returns info."""
+        nblk, B = _blocks(psi, self.grid)
+        info = ctypes.c_int32(0)
+        check(lib().rs_orthonormalize_block(
+            self._h, _dev(psi, "psi"), nblk, B, _dtype_code(psi), self._prec(psi, prec),
+            _dev(S_out, "S_out") if S_out is not None else None, ctypes.byref(info),
+            _stream(stream)))
+        return info.value
+
+    def subspace_diag(self, psi, hpsi, prec=None, stream=None):
+        """Rayleigh-Ritz in place (rs_subspace_diag); returns eigenvalues."""
+        nblk, B = _blocks(psi, self.grid)
+        torch = _torch()
+        ev = torch.empty(nblk * B, dtype=torch.float64, device=psi.device)
+        check(lib().rs_subspace_diag(self._h, _dev(psi, "psi"), _dev(hpsi, "hpsi"), _dev(ev, "eig"),
+                                     nblk, B, _dtype_code(psi), self._prec(psi, prec),
+                                     _stream(stream)))
+        return ev
+
+
 def to_blocks(states: np.ndarray, B: int) -> np.ndarray:
     """State-major [N, np] -> block layout [N/B, np, B] (host-side reshuffle)."""
     N, npts = states.shape

@@ -46,6 +46,14 @@ SIGNATURES = {
     "rs_hpsi_block": (ctypes.c_int, [P, P, P, P, P, I32, I32, I32, P]),
     "rs_project_nl": (ctypes.c_int, [P, P, P, P, I32, I32, I32, P]),
     "rs_apply_nl": (ctypes.c_int, [P, P, P, P, I32, I32, I32, P]),
+    "rs_ctx_create": (ctypes.c_int, [P, I32, ctypes.POINTER(P)]),
+    "rs_ctx_destroy": (None, [P]),
+    "rs_overlap": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P]),
+    "rs_rotate": (ctypes.c_int, [P, P, P, I32, I32, I32, I32, P]),
+    "rs_cholesky": (ctypes.c_int, [P, P, P, I32, P, P]),
+    "rs_eigh": (ctypes.c_int, [P, P, P, P, I32, P]),
+    "rs_orthonormalize_block": (ctypes.c_int, [P, P, I32, I32, I32, I32, P, PI32, P]),
+    "rs_subspace_diag": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P]),
 }
 
 _lib = None

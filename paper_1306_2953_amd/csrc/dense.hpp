@@ -1,0 +1,36 @@
+// Dense (N x N) stage of orthogonalisation and subspace diagonalisation.
+#pragma once
+
+#include <vector>
+
+#include "internal.hpp"
+
+namespace rs {
+
+// Workspace of the point-summed contractions and small-matrix kernels,
+// sized for max_states at creation (the field calls never allocate).
+struct DenseWork {
+    int max_states = 0;
+    int max_chunks = 512;
+    DevBuf partial;                    // double [max_chunks][N16][N16]
+    std::vector<int2> blocks_syrk, blocks_full;
+    int blocks_n = 0;
+    DevBuf d_blocks_syrk, d_blocks_full;
+    DevBuf mwork;                      // double [N][N] scratch
+    DevBuf xth, xtm, xtl;              // bfloat16 [N16][N32] three-term split rotation matrix
+    DevBuf sweeps;                     // int
+};
+
+rs_status dense_work_init(DenseWork &w, int64_t np, int max_states);
+// S = dv X^T Y over points; mode 0 plain, 2 symmetrised (X == Y is computed
+// as a symmetric rank-k product).
+rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, int nblk, int dtype,
+               int prec, double dv, double *S, int mode, hipStream_t st);
+// psi <- psi X in place (skipped when *skip != 0, if skip is given).
+rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, int nblk, int dtype,
+                 int prec, const int *skip, hipStream_t st);
+rs_status cholesky(DenseWork &w, const double *S, double *U, int N, int *info_dev, hipStream_t st);
+rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStream_t st);
+rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st);
+
+}  // namespace rs

@@ -151,7 +151,7 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
                     BrickRec &r = g->bricks_host[b];
                     r.mask = 0;
                     r.start = (int32_t)brick_first[b];
-                    r.reserved = 0;
+                    r.flags = 0;
                     for (int s = 0; s < 64; ++s) {
                         const int64_t i = bx * 4 + (s & 3), j = by * 4 + ((s >> 2) & 3), k = bz * 4 + (s >> 4);
                         if (is_in(i, j, k)) r.mask |= (uint64_t)1 << s;
@@ -171,8 +171,44 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
                             r.nbr[a * 2 + sgn] = nbid;
                         }
                 }
+        for (int64_t b = 0; b < nbricks; ++b) {
+            BrickRec &r = g->bricks_host[b];
+            bool fast = r.mask == ~0ull;
+            for (int f = 0; f < 6 && fast; ++f)
+                fast = r.nbr[f] >= 0 && g->bricks_host[r.nbr[f]].mask == ~0ull;
+            r.flags = fast ? kBrickFast : 0;
+        }
+        // execution order: bricks sorted along a Z-order (Morton) curve of
+        // their lattice coordinates, so that bricks processed together are
+        // spatially compact and their neighbours stay in cache
+        std::vector<std::pair<uint64_t, int32_t>> key;
+        key.reserve(nbricks);
+        for (int64_t bz = 0; bz < nbz; ++bz)
+            for (int64_t by = 0; by < nby; ++by)
+                for (int64_t bx = 0; bx < nbx; ++bx) {
+                    const int32_t b = g->brick_map[(bz * nby + by) * nbx + bx];
+                    if (b < 0) continue;
+                    uint64_t m = 0;
+                    for (int bit = 0; bit < 21; ++bit) {
+                        m |= (uint64_t)((bx >> bit) & 1) << (3 * bit);
+                        m |= (uint64_t)((by >> bit) & 1) << (3 * bit + 1);
+                        m |= (uint64_t)((bz >> bit) & 1) << (3 * bit + 2);
+                    }
+                    key.emplace_back(m, b);
+                }
+        std::sort(key.begin(), key.end());
+        std::vector<int32_t> order;
+        order.reserve(nbricks);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int64_t i = 0; i < nbricks; ++i) {
+                const bool fast = (g->bricks_host[key[i].second].flags & kBrickFast) != 0;
+                if (fast == (pass == 0)) order.push_back(key[i].second);
+            }
+        g->nfast = 0;
+        for (int64_t b = 0; b < nbricks; ++b) g->nfast += (g->bricks_host[b].flags & kBrickFast) != 0;
         if (!g->host_only) {
             rs_status st = g->bricks.upload(g->bricks_host);
+            if (!st) st = g->exec.upload(order);
             if (st) { delete g; return st; }
         }
     }

@@ -62,175 +62,262 @@ __device__ __forceinline__ T ld_slot(rsrc_t r, uint64_t mask, int start, int q, 
     return bload<T>(r, slot_off(mask, start, q, B * sizeof(T)) + lane_off);
 }
 
-template <typename T>
-__device__ __forceinline__ T line_term(const T *v, int i, T c1, T c2, T c3, T c4) {
-    // v[0..]: a line of values with 4 before output i's centre (at v[4+i]).
-    const T c0v = v[4 + i];
-    T t = c1 * ((v[5 + i] - c0v) + (v[3 + i] - c0v));
-    t += c2 * ((v[6 + i] - c0v) + (v[2 + i] - c0v));
-    t += c3 * ((v[7 + i] - c0v) + (v[1 + i] - c0v));
-    t += c4 * ((v[8 + i] - c0v) + (v[0 + i] - c0v));
-    return t;
+// Weights of the stencil written on first differences d_k = v_{k+1} - v_k:
+// sum_m c_m (v_{i+m} + v_{i-m} - 2 v_i) = sum_j W_j (d_{i+j} - d_{i-1-j}),
+// W_j = sum_{m>j} c_m.  Differences of neighbouring values are exact or
+// nearly so, so the cancellation of the plain form (c_0 = -2 sum c_m) never
+// happens in FP32, and a line of n values costs n-1 subtractions shared by
+// its outputs plus 8 operations per output.
+struct StencilW { double w0, w1, w2, w3; };
+
+template <typename T, int N>
+__device__ __forceinline__ void line_lap(const T (&v)[N], T (&lap)[N - 8], T w0, T w1, T w2, T w3) {
+    T d[N - 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) d[k] = v[k + 1] - v[k];
+#pragma unroll
+    for (int i = 0; i < N - 8; ++i) {
+        const int p = 4 + i;
+        T t = w0 * (d[p] - d[p - 1]);
+        t += w1 * (d[p + 1] - d[p - 2]);
+        t += w2 * (d[p + 2] - d[p - 3]);
+        t += w3 * (d[p + 3] - d[p - 4]);
+        lap[i] = t;
+    }
 }
 
-// Hides a value from common-subexpression elimination so that slot offsets
-// are recomputed (two integer ops) instead of being kept live in registers.
-__device__ __forceinline__ uint64_t opaque(uint64_t m) {
-    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-    asm volatile("" : "+v"(lo), "+v"(hi));
-    return ((uint64_t)hi << 32) | lo;
+// Uniform buffer loads with the slot offset in a scalar register and the
+// lane offset (plus a compile-time immediate) in a vector register.
+template <typename T> __device__ __forceinline__ T bload_s(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float bload_s<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double bload_s<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
-// One lane group (B lanes, one state each) computes NZ z-planes (16 points
-// each) of one brick, starting at plane Z0; NZ = 4 is the whole brick, NZ = 2
-// half of it (used for FP64 to halve the register footprint).  The planes'
-// own values stay in registers; every neighbour-brick value is loaded once.
-template <typename T, int B, int NZ, int Z0>
+// Locates slot q of a brick.  FAST: the brick is full, so slot q is point
+// start + q; the byte offset splits into a scalar base per group of K slots
+// and an immediate (q mod K) * ROW that fits the instruction's 12-bit offset
+// field.  Otherwise the offsets come from a table in LDS that the wave fills
+// first; empty slots hold kOOB and the lane offset is added with unsigned
+// saturation, so their loads return 0 and their stores are dropped.
+template <typename T, int ROW, bool FAST>
+struct Slots {
+    static constexpr int K = (4096 / ROW) >= 64 ? 64 : (4096 / ROW);
+    int start;
+    uint32_t base;            // FAST: start * ROW
+    const uint32_t *tbl;      // !FAST: 64 byte offsets in LDS
+    __device__ __forceinline__ T load(rsrc_t r, uint32_t lane_off, int q) const {
+        if constexpr (FAST)
+            return bload_s<T>(r, lane_off + (uint32_t)((q % K) * ROW), base + (uint32_t)((q / K) * K * ROW));
+        else
+            return bload<T>(r, __builtin_elementwise_add_sat(lane_off, tbl[q]));
+    }
+    __device__ __forceinline__ void store(T v, rsrc_t r, uint32_t lane_off, int q) const {
+        if constexpr (FAST) {
+            if constexpr (sizeof(T) == 4)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r,
+                                                      (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW), 0);
+            else {
+                typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r,
+                                                      (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW), 0);
+            }
+        } else {
+            bstore<T>(v, r, __builtin_elementwise_add_sat(lane_off, tbl[q]));
+        }
+    }
+    __device__ __forceinline__ bool has(int q) const {
+        if constexpr (FAST) return true;
+        else return tbl[q] != kOOB;
+    }
+    // point index of an occupied slot q
+    __device__ __forceinline__ int point(int q) const {
+        if constexpr (FAST) return start + q;
+        else return (int)(tbl[q] / ROW);
+    }
+};
+
+// One wave computes NZ z-planes (from plane Z0) of one brick for 64 state
+// columns: lane l is state (c mod B) of block (c / B), c = 64*colgroup + l.
+// Everything that locates points (brick records, masks, offsets) is uniform
+// in the wave and lives in scalar registers; a lane's address is its column
+// offset plus the uniform slot offset.
+template <typename T, int ROW, int NZ, int Z0, bool FAST>
 __device__ __forceinline__ void
-hpsi_brick_body(const BrickRec *__restrict__ bricks, int b, int blk,
-                const T *__restrict__ psi, T *__restrict__ hpsi, const T *__restrict__ vloc,
-                int64_t blk_stride, T pre, T c1, T c2, T c3, T c4,
-                const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
-                const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
-                const T *__restrict__ dp, int nat) {
-    constexpr int NP = 16 * NZ;             // points per lane group
-    constexpr int z0 = Z0;
-    const int s = threadIdx.x % B;
-    const uint32_t fbytes = (uint32_t)(blk_stride * sizeof(T));
-    const rsrc_t rp = make_rsrc(psi + blk * blk_stride, fbytes);
-    const rsrc_t rh = make_rsrc(hpsi + blk * blk_stride, fbytes);
-    const rsrc_t rv = make_rsrc(vloc, (uint32_t)(blk_stride / B * sizeof(T)));
-    const uint32_t lo = s * sizeof(T);
-
-    const BrickRec br = bricks[b];
-    uint64_t nm[6];
-    int ns[6];
+hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t rp, rsrc_t rh,
+          uint32_t lane_off, const uint32_t *tbl, const T *__restrict__ vloc, T pre, T w0, T w1,
+          T w2, T w3, const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
+          const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
+          const T *__restrict__ dpl, int dps) {
+    constexpr int NP = 16 * NZ;
+    Slots<T, ROW, FAST> nb[6], me;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int j = br.nbr[f];
-        nm[f] = j >= 0 ? bricks[j].mask : 0ull;
-        ns[f] = j >= 0 ? bricks[j].start : 0;
+        nb[f].start = j >= 0 ? bricks[j].start : 0;
+        nb[f].base = (uint32_t)nb[f].start * ROW;
+        nb[f].tbl = tbl + (f + 1) * 64;
     }
-    const int s0 = br.start;
-    uint64_t m0 = br.mask;
+    me.start = br.start;
+    me.base = (uint32_t)br.start * ROW;
+    me.tbl = tbl;
 
     T own[NP], acc[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int q = z0 * 16 + k;
-        own[k] = ld_slot<T, B>(rp, m0, s0, q, lo);
-        acc[k] = bload<T>(rv, slot_off(m0, s0, q, sizeof(T))) * own[k];
+        own[k] = me.load(rp, lane_off, Z0 * 16 + k);
     }
     // x lines
 #pragma unroll
     for (int zz = 0; zz < NZ; ++zz)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-            T v[12];
+            T v[12], lap[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
-                const int q = ((z0 + zz) * 4 + y) * 4 + x;
-                v[x] = ld_slot<T, B>(rp, nm[0], ns[0], q, lo);
+                const int q = ((Z0 + zz) * 4 + y) * 4 + x;
+                v[x] = nb[0].load(rp, lane_off, q);
                 v[4 + x] = own[(zz * 4 + y) * 4 + x];
-                v[8 + x] = ld_slot<T, B>(rp, nm[1], ns[1], q, lo);
+                v[8 + x] = nb[1].load(rp, lane_off, q);
             }
+            line_lap<T, 12>(v, lap, w0, w1, w2, w3);
 #pragma unroll
-            for (int x = 0; x < 4; ++x) acc[(zz * 4 + y) * 4 + x] += pre * line_term(v, x, c1, c2, c3, c4);
-            __builtin_amdgcn_sched_barrier(0);
+            for (int x = 0; x < 4; ++x) acc[(zz * 4 + y) * 4 + x] = lap[x];
         }
     // y lines
 #pragma unroll
     for (int zz = 0; zz < NZ; ++zz)
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-            T v[12];
+            T v[12], lap[4];
 #pragma unroll
             for (int y = 0; y < 4; ++y) {
-                const int q = ((z0 + zz) * 4 + y) * 4 + x;
-                v[y] = ld_slot<T, B>(rp, nm[2], ns[2], q, lo);
+                const int q = ((Z0 + zz) * 4 + y) * 4 + x;
+                v[y] = nb[2].load(rp, lane_off, q);
                 v[4 + y] = own[(zz * 4 + y) * 4 + x];
-                v[8 + y] = ld_slot<T, B>(rp, nm[3], ns[3], q, lo);
+                v[8 + y] = nb[3].load(rp, lane_off, q);
             }
+            line_lap<T, 12>(v, lap, w0, w1, w2, w3);
 #pragma unroll
-            for (int y = 0; y < 4; ++y) acc[(zz * 4 + y) * 4 + x] += pre * line_term(v, y, c1, c2, c3, c4);
-            __builtin_amdgcn_sched_barrier(0);
+            for (int y = 0; y < 4; ++y) acc[(zz * 4 + y) * 4 + x] += lap[y];
         }
-    // z lines: a column of NZ + 8 values around the lane group's planes
-    m0 = opaque(m0);
+    // z lines: NZ + 8 values around this wave's planes
 #pragma unroll
     for (int y = 0; y < 4; ++y)
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-            T v[NZ + 8];
+            T v[NZ + 8], lap[NZ];
 #pragma unroll
             for (int j = 0; j < NZ + 8; ++j) {
-                const int z = z0 - 4 + j;       // brick-local z of column entry j
-                if (z < 0) {
-                    v[j] = ld_slot<T, B>(rp, nm[4], ns[4], ((z + 4) * 4 + y) * 4 + x, lo);
-                } else if (z >= 4) {
-                    v[j] = ld_slot<T, B>(rp, nm[5], ns[5], ((z - 4) * 4 + y) * 4 + x, lo);
-                } else if (z >= z0 && z < z0 + NZ) {
-                    v[j] = own[((z - z0) * 4 + y) * 4 + x];
-                } else {
-                    v[j] = ld_slot<T, B>(rp, m0, s0, (z * 4 + y) * 4 + x, lo);
-                }
+                const int z = Z0 - 4 + j;
+                if (z < 0) v[j] = nb[4].load(rp, lane_off, ((z + 4) * 4 + y) * 4 + x);
+                else if (z >= 4) v[j] = nb[5].load(rp, lane_off, ((z - 4) * 4 + y) * 4 + x);
+                else if (z >= Z0 && z < Z0 + NZ) v[j] = own[((z - Z0) * 4 + y) * 4 + x];
+                else v[j] = me.load(rp, lane_off, (z * 4 + y) * 4 + x);
             }
+            line_lap<T, NZ + 8>(v, lap, w0, w1, w2, w3);
 #pragma unroll
-            for (int zz = 0; zz < NZ; ++zz) acc[(zz * 4 + y) * 4 + x] += pre * line_term(v, zz, c1, c2, c3, c4);
-            __builtin_amdgcn_sched_barrier(0);
+            for (int zz = 0; zz < NZ; ++zz) acc[(zz * 4 + y) * 4 + x] += lap[zz];
         }
+    // local potential
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int q = Z0 * 16 + k;
+        const T vp = me.has(q) ? vloc[me.point(q)] : T(0);
+        acc[k] = pre * acc[k] + vp * own[k];
+    }
     // non-local part 2, point-centric: sum over the atoms whose sphere holds
     // the point of gamma_A,i(p) * (D_A,i P_A,i,s)
-    m0 = opaque(m0);
     if (brick_nl != nullptr && brick_nl[b]) {
-        const T *dpb = dp + (int64_t)blk * nat * 4 * B;
+        const int q4 = dps / 4;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const int q = z0 * 16 + k;
-            if ((m0 >> q) & 1ull) {
-                const int p = s0 + __popcll(m0 & ((1ull << q) - 1ull));
-                const int k1 = pt_ptr[p + 1];
-                for (int e = pt_ptr[p]; e < k1; ++e) {
+                const int q = Z0 * 16 + k;
+            if (me.has(q)) {
+                const int p = me.point(q);
+                const int e1 = pt_ptr[p + 1];
+                for (int e = pt_ptr[p]; e < e1; ++e) {
                     const T *g = ent_gamma + 4 * (int64_t)e;
-                    const T *d = dpb + ent_atom[e] * 4 * B + s;
-                    acc[k] += g[0] * d[0] + g[1] * d[B] + g[2] * d[2 * B] + g[3] * d[3 * B];
+                    const T *d = dpl + ent_atom[e] * dps;
+                    acc[k] += g[0] * d[0] + g[1] * d[q4] + g[2] * d[2 * q4] + g[3] * d[3 * q4];
                 }
             }
         }
     }
-    m0 = opaque(m0);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int q = z0 * 16 + k;
-        bstore<T>(acc[k], rh, slot_off(m0, s0, q, B * sizeof(T)) + lo);
+        me.store(acc[k], rh, lane_off, Z0 * 16 + k);
     }
 }
 
-// Work-group = 4 waves.  With PARTS = 4/NZ lane groups per brick, wave w
-// handles part w % PARTS of its bricks, so the part is uniform in a wave.
-template <typename T, int B, int NZ>
+// Work-group = 4 waves.  blockIdx.y selects a group of 64 state columns;
+// blockIdx.x (XCD-remapped) a run of bricks from `exec` (one of two lists:
+// interior bricks, FAST, whose neighbours are all full, and the rest).  A
+// brick is split into 4/NZ parts of NZ z-planes, one wave each.  B is a
+// template parameter so that the row size B * sizeof(T) is a constant.
+template <typename T, int B, int NZ, bool FAST>
 __global__ void __launch_bounds__(256)
-hpsi_brick_kernel(const BrickRec *__restrict__ bricks, int nbricks, int nwg, int nwg_pad,
-                  const T *__restrict__ psi, T *__restrict__ hpsi, const T *__restrict__ vloc,
-                  int64_t blk_stride, T pre, T c1, T c2, T c3, T c4,
+hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict__ exec,
+                  int nexec, int nwg, int nwg_pad, const T *__restrict__ psi,
+                  T *__restrict__ hpsi, const T *__restrict__ vloc, int64_t np, int nblk,
+                  T pre, T w0, T w1, T w2, T w3,
                   const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
                   const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
                   const T *__restrict__ dp, int nat) {
     constexpr int PARTS = 4 / NZ;
-    constexpr int GPW = 64 / B;                 // lane groups per wave
-    constexpr int BPWG = 4 * GPW / PARTS;       // bricks per work-group
+    constexpr int ROW = B * (int)sizeof(T);
+    __shared__ uint32_t tbl_all[FAST ? 1 : 4 * 7 * 64];
     const int wg = xcd_remap(blockIdx.x, nwg_pad);
     if (wg >= nwg) return;
-    const int wave = threadIdx.x / 64;
-    const int part = wave % PARTS;
-    const int b = wg * BPWG + (wave / PARTS) * GPW + (threadIdx.x % 64) / B;
-    if (b >= nbricks) return;
-    if (part == 0)
-        hpsi_brick_body<T, B, NZ, 0>(bricks, b, blockIdx.y, psi, hpsi, vloc, blk_stride, pre, c1, c2,
-                                     c3, c4, brick_nl, pt_ptr, ent_atom, ent_gamma, dp, nat);
-    else if constexpr (PARTS == 2)
-        hpsi_brick_body<T, B, NZ, 2>(bricks, b, blockIdx.y, psi, hpsi, vloc, blk_stride, pre, c1, c2,
-                                     c3, c4, brick_nl, pt_ptr, ent_atom, ent_gamma, dp, nat);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int slot = (wg * 4 + wave) / PARTS;
+    const int part = (wg * 4 + wave) % PARTS;
+    const int lane = threadIdx.x & 63;
+    const uint32_t *tbl = nullptr;
+    if constexpr (!FAST) {
+        // slot byte offsets of this brick and its six neighbours, one lane
+        // per slot: rank of the slot among the occupied ones, or kOOB
+        uint32_t *t = tbl_all + wave * 7 * 64;
+        const int bb = slot < nexec ? exec[slot] : -1;
+#pragma unroll
+        for (int f = 0; f < 7; ++f) {
+            const int j = bb < 0 ? -1 : (f == 0 ? bb : bricks[bb].nbr[f - 1]);
+            uint32_t off = kOOB;
+            if (j >= 0) {
+                const uint64_t m = bricks[j].mask;
+                if ((m >> lane) & 1ull)
+                    off = (uint32_t)(bricks[j].start + __popcll(m & ((1ull << lane) - 1ull))) * ROW;
+            }
+            t[f * 64 + lane] = off;
+        }
+        __syncthreads();
+        tbl = t;
+    }
+    if (slot >= nexec) return;
+    const int b = exec[slot];
+    const int col = blockIdx.y * 64 + lane;
+    const int blk0 = (blockIdx.y * 64) / B;          // first block of this column group
+    const int blk = col / B;
+    if (blk >= nblk) return;
+    const int s = col % B;
+    const int nb_here = min(nblk - blk0, 64 / B);
+    const int64_t blk_elems = np * B;
+    const uint32_t bytes = (uint32_t)(nb_here * blk_elems * sizeof(T));
+    const rsrc_t rp = make_rsrc(psi + blk0 * blk_elems, bytes);
+    const rsrc_t rh = make_rsrc(hpsi + blk0 * blk_elems, bytes);
+    const uint32_t lane_off = (uint32_t)(((blk - blk0) * blk_elems + s) * sizeof(T));
+    const T *dpl = dp ? dp + (int64_t)blk * nat * 4 * B + s : nullptr;
+    const int dps = 4 * B;
+    const BrickRec br = bricks[b];
+#define RS_PART(ZZ)                                                                            \
+    hpsi_wave<T, ROW, NZ, ZZ, FAST>(br, bricks, b, rp, rh, lane_off, tbl, vloc, pre, w0, w1, w2, w3, \
+                                    brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, dps)
+    if (part == 0) RS_PART(0);
+    if constexpr (PARTS >= 2) { if (part == 1) RS_PART(NZ); }
+    if constexpr (PARTS == 4) { if (part == 2) RS_PART(2 * NZ); if (part == 3) RS_PART(3 * NZ); }
+#undef RS_PART
 }
 
 // Non-local part 1 (eq. 6 integrals), stage 1: one work-group per (chunk of
@@ -322,6 +409,13 @@ nl_apply_kernel(const int32_t *__restrict__ pt_ptr, const int32_t *__restrict__ 
     *y = *y + acc;
 }
 
+#ifndef RS_NZF32
+#define RS_NZF32 2
+#endif
+#ifndef RS_NZF64
+#define RS_NZF64 1
+#endif
+
 bool pow2_block(int B) { return B >= 1 && B <= 64 && (B & (B - 1)) == 0; }
 
 template <typename T>
@@ -355,38 +449,53 @@ template <typename T>
 rs_status launch_hpsi(const rs_grid *g, const rs_nl *nl, const T *vloc, const T *psi, T *hpsi,
                       int nblk, int B, hipStream_t st) {
     if (g->nbricks == 0) return RS_OK;
-    if ((uint64_t)g->np * B * sizeof(T) > kMaxField)
-        return fail(RS_ENOTSUP, "rs_hpsi_block: one block of fields exceeds 4 GiB");
+    if ((uint64_t)g->np * 64 * sizeof(T) > kMaxField)
+        return fail(RS_ENOTSUP, "rs_hpsi_block: 64 state columns of the grid exceed 4 GiB");
     const bool with_nl = nl != nullptr && nl->nat > 0;
     if (with_nl) {
         rs_status s = launch_project<T>(g, nl, psi, nullptr, nblk, B, st);
         if (s) return s;
     }
-    const double c[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    const double c1 = 8.0 / 5.0, c2 = -1.0 / 5.0, c3 = 8.0 / 315.0, c4 = -1.0 / 560.0;
     const T pre = (T)(-0.5 / (g->h * g->h));
-    constexpr int NZ = sizeof(T) == 8 ? 2 : 4;
-    const int bpwg = 4 * (64 / B) / (4 / NZ);
-    const int nwg = (int)((g->nbricks + bpwg - 1) / bpwg);
-    const int nwg_pad = (nwg + 7) & ~7;
-    dim3 grid(nwg_pad, nblk);
-    const int64_t stride = g->np * B;
+    const int ncg = (nblk * B + 63) / 64;
     const int32_t *bnl = with_nl ? nl->brick_nl.as<int32_t>() : nullptr;
     const int32_t *ptp = with_nl ? nl->pt_ptr.as<int32_t>() : nullptr;
     const int32_t *eat = with_nl ? nl->ent_atom.as<int32_t>() : nullptr;
     const T *egm = with_nl ? (sizeof(T) == 8 ? (const T *)nl->ent_gamma64.p : (const T *)nl->ent_gamma32.p) : nullptr;
     const T *dp = with_nl ? (const T *)nl->dp.p : nullptr;
     const int nat = with_nl ? nl->nat : 0;
-#define RS_HPSI(BB)                                                                          \
-    case BB:                                                                                 \
-        hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZ>), grid, dim3(256), 0, st,              \
-                           g->bricks.as<BrickRec>(), (int)g->nbricks, nwg, nwg_pad, psi,    \
-                           hpsi, vloc, stride, pre, (T)c[1], (T)c[2], (T)c[3], (T)c[4],      \
-                           bnl, ptp, eat, egm, dp, nat);                                     \
+    const T w0 = (T)(c1 + c2 + c3 + c4), w1 = (T)(c2 + c3 + c4), w2 = (T)(c3 + c4), w3 = (T)c4;
+    // interior bricks: whole brick per wave in FP32, half in FP64; surface
+    // bricks: half (FP32) or a quarter (FP64) per wave
+    constexpr int NZF = sizeof(T) == 8 ? RS_NZF64 : RS_NZF32;
+    constexpr int NZS = sizeof(T) == 8 ? 1 : 2;
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fast = pass == 0;
+        const int64_t nexec = fast ? g->nfast : g->nbricks - g->nfast;
+        if (nexec == 0) continue;
+        const int32_t *ex = g->exec.as<int32_t>() + (fast ? 0 : g->nfast);
+        const int parts = 4 / (fast ? NZF : NZS);
+        const int nwg = (int)((nexec * parts + 3) / 4);
+        const int nwg_pad = (nwg + 7) & ~7;
+        dim3 grid(nwg_pad, ncg);
+#define RS_HPSI(BB)                                                                                \
+    case BB:                                                                                       \
+        if (fast)                                                                                  \
+            hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZF, true>), grid, dim3(256), 0, st,     \
+                               g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
+                               vloc, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, dp, nat); \
+        else                                                                                       \
+            hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZS, false>), grid, dim3(256), 0, st,    \
+                               g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
+                               vloc, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, dp, nat); \
         break;
-    switch (B) {
-        RS_HPSI(1) RS_HPSI(2) RS_HPSI(4) RS_HPSI(8) RS_HPSI(16) RS_HPSI(32) RS_HPSI(64)
-    }
+        switch (B) {
+            RS_HPSI(1) RS_HPSI(2) RS_HPSI(4) RS_HPSI(8) RS_HPSI(16) RS_HPSI(32) RS_HPSI(64)
+        }
 #undef RS_HPSI
+        RS_HIP(hipGetLastError());
+    }
     RS_HIP(hipGetLastError());
     return RS_OK;
 }

@@ -60,11 +60,13 @@ struct DevBuf {
 // slot = (z*4 + y)*4 + x).  `start` is the index of the brick's first inner
 // point; the point in slot q is start + popcount(mask & ((1<<q)-1)) when bit
 // q of mask is set.  nbr: neighbouring bricks along -x,+x,-y,+y,-z,+z
-// (-1 = none, i.e. all zeros).
+// (-1 = none, i.e. all zeros).  flags & kBrickFast: the brick and its six
+// neighbours all exist and hold 64 points each.
+constexpr int32_t kBrickFast = 1;
 struct BrickRec {
     uint64_t mask;
     int32_t start;
-    int32_t reserved;
+    int32_t flags;
     int32_t nbr[6];
 };
 static_assert(sizeof(BrickRec) == 40, "BrickRec layout");
@@ -92,6 +94,9 @@ struct rs_grid {
     int64_t nbricks = 0;
     std::vector<rs::BrickRec> bricks_host;
     rs::DevBuf bricks;       // BrickRec[nbricks]
+    rs::DevBuf exec;         // int32[nbricks]: fast bricks, then the others,
+                             // each list in Morton (Z-curve) order
+    int64_t nfast = 0;
     int64_t lattice_index(int64_t i, int64_t j, int64_t k) const {
         return ((k - lo[2]) * L[1] + (j - lo[1])) * L[0] + (i - lo[0]);
     }
