@@ -59,9 +59,10 @@ typedef int rs_status;
  * split as a = a_hi + a_lo (each bfloat16, round to nearest even); products
  * on matrix cores with FP32 accumulation.  Overlaps: a_hi b_hi + a_hi b_lo +
  * a_lo b_hi + a_lo b_lo (the last keeps norms unbiased), partial sums over
- * chunks of <= 4096 points added in FP64.  Rotations: the FP64 matrix is
- * split in three bfloat16 terms x_0 + x_1 + x_2 and multiplied by a_hi and
- * a_lo (5 products), so no common scale error reaches a whole state. */
+ * chunks of <= 4096 points added in FP64.  Rotations: field and FP64 matrix
+ * are both split in three bfloat16 terms and the six products a_i x_j with
+ * i + j <= 2 are summed in FP32, which keeps the rotated field at FP32
+ * accuracy. */
 #define RS_PREC_NATIVE 0
 #define RS_PREC_BF16X3 1
 
@@ -226,6 +227,53 @@ rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk, int32_t B,
  * ascending.  Asynchronous. */
 rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_t nblk,
                            int32_t B, int32_t dtype, int32_t prec, void *stream);
+
+/* ------------------------------------------------- eigensolver, Sec. 3
+ * RMM-DIIS with the filter preconditioner and the block stopping rule of
+ * Sec. 9.  One rs_eigensolve_step:
+ *   1. H psi for all states; Rayleigh-Ritz (eqs. (9)-(10)); eig = its
+ *      eigenvalues (ascending).
+ *   2. Per state: eps0 = <psi|H psi>/<psi|psi>, R0 = H psi - eps0 psi,
+ *      resnorm = ||R0||.  A block whose states all have resnorm < tol is
+ *      frozen for the rest of the step (when block_stop).
+ *   3. d = K R0 with K r = alpha r + (1 - alpha)/6 (sum of the six nearest
+ *      neighbours); lambda minimises the Rayleigh quotient of psi + lambda d;
+ *      psi_1 = psi + lambda d.
+ *   4. For j = 1 .. m-1: the residuals R_i = H psi_i - eps_i psi_i of the
+ *      iterates so far are combined with coefficients c minimising
+ *      ||sum c R|| / ||sum c psi|| (lowest generalised eigenvector, written in
+ *      the basis {psi_L, psi_i - psi_L}, c_0 = 1); psi_{j+1} = sum c psi +
+ *      lambda K (sum c R), H psi_{j+1} updated linearly.
+ *   5. psi <- newest iterate, then orthonormalised (Cholesky, eq. (8)).
+ * Applications of H per step: 1 + m.  FP32 fields use the split-BF16
+ * contractions of RS_PREC_BF16X3; every inner product is accumulated in
+ * FP64 and the small per-state problems are solved in FP64. */
+typedef struct rs_solver rs_solver;
+typedef struct {
+    int32_t m;           /* iterates built per step (H d applications), 1..3 */
+    double  alpha;       /* filter centre weight (1/2)                       */
+    double  tol;         /* residual threshold of the block stopping rule    */
+    int32_t block_stop;  /* nonzero: freeze blocks whose states are all < tol */
+} rs_solver_opts;
+
+/* nstates (a multiple of B, <= 256) states of dtype on grid g with local
+ * potential vloc (DEVICE [np] of dtype; must stay valid for the solver's
+ * lifetime) and optional projectors nl.  opts NULL: m = 3, alpha = 1/2,
+ * tol = 1e-6, block_stop = 1.  Allocates all workspaces (about 2(m+1)+3
+ * field arrays of np * nstates elements). */
+rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc,
+                               int32_t nstates, int32_t B, int32_t dtype,
+                               const rs_solver_opts *opts, rs_solver **out);
+void rs_eigensolve_destroy(rs_solver *s);
+
+/* One step on psi (DEVICE [nstates/B][np][B], orthonormal on entry; updated
+ * in place).  eig and resnorm (HOST double [nstates], may be NULL) receive
+ * the step's Rayleigh-Ritz eigenvalues and residual norms; *nconv (HOST, may
+ * be NULL) the number of states with resnorm < tol.  Synchronises the stream
+ * once.  Errors: RS_ENOTPOSDEF if the final orthonormalisation fails,
+ * RS_ENONFINITE if an eigenvalue or residual is not finite. */
+rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, double *resnorm,
+                             int32_t *nconv, void *stream);
 
 #ifdef __cplusplus
 }

@@ -274,6 +274,41 @@ class Context:
         return ev
 
 
+class Eigensolver:
+    """RMM-DIIS eigensolver over the states of one grid (rs_solver)."""
+
+    def __init__(self, grid: Grid, nl: Optional[NonLocal], vloc, nstates: int, B: int,
+                 m: int = 3, alpha: float = 0.5, tol: float = 1e-6, block_stop: bool = True):
+        self.grid, self.nl, self.vloc = grid, nl, vloc     # vloc kept alive here
+        self.nstates, self.B = nstates, B
+        o = _abi.SolverOpts()
+        o.m, o.alpha, o.tol, o.block_stop = int(m), float(alpha), float(tol), int(block_stop)
+        self._h = ctypes.c_void_p()
+        check(lib().rs_eigensolve_create(grid.handle, nl.handle if nl is not None else None,
+                                         _dev(vloc, "vloc"), int(nstates), int(B),
+                                         _dtype_code(vloc), ctypes.byref(o), ctypes.byref(self._h)))
+
+    def step(self, psi, stream=None):
+        """One step in place; returns (eig, resnorm, nconv) on the host."""
+        nblk, B = _blocks(psi, self.grid)
+        if nblk * B != self.nstates or B != self.B:
+            raise ValueError("psi does not match the solver's states")
+        eig = np.empty(self.nstates)
+        res = np.empty(self.nstates)
+        nconv = ctypes.c_int32(0)
+        check(lib().rs_eigensolve_step(
+            self._h, _dev(psi, "psi"), eig.ctypes.data_as(_abi.PF64),
+            res.ctypes.data_as(_abi.PF64), ctypes.byref(nconv), _stream(stream)))
+        return eig, res, nconv.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_eigensolve_destroy(h)
+            self._h = None
+
+
 def to_blocks(states: np.ndarray, B: int) -> np.ndarray:
     """State-major [N, np] -> block layout [N/B, np, B] (host-side reshuffle)."""
     N, npts = states.shape

@@ -26,6 +26,10 @@ PI64 = ctypes.POINTER(ctypes.c_int64)
 PF64 = ctypes.POINTER(ctypes.c_double)
 
 
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("m", I32), ("alpha", F64), ("tol", F64), ("block_stop", I32)]
+
+
 class GridDesc(ctypes.Structure):
     _fields_ = [("kind", I32), ("h", F64), ("n", I32), ("radius", F64),
                 ("brick", I32 * 3), ("flags", I32)]
@@ -54,6 +58,9 @@ SIGNATURES = {
     "rs_eigh": (ctypes.c_int, [P, P, P, P, I32, P]),
     "rs_orthonormalize_block": (ctypes.c_int, [P, P, I32, I32, I32, I32, P, PI32, P]),
     "rs_subspace_diag": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P]),
+    "rs_eigensolve_create": (ctypes.c_int, [P, P, P, I32, I32, I32, P, ctypes.POINTER(P)]),
+    "rs_eigensolve_destroy": (None, [P]),
+    "rs_eigensolve_step": (ctypes.c_int, [P, P, PF64, PF64, PI32, P]),
 }
 
 _lib = None

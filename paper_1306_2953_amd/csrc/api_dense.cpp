@@ -108,16 +108,21 @@ extern "C" rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk,
     return RS_OK;
 }
 
-extern "C" rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_t nblk, int32_t B,
-                                      int32_t dtype, int32_t prec, void *stream) {
+rs_status subspace_diag_capped(rs_ctx *c, void *psi, void *hpsi, double *eig, int nblk, int B, int dtype,
+                               int prec, int max_sweeps, hipStream_t s) {
     rs_status st = check(c, nblk, B, dtype, prec, "rs_subspace_diag");
     if (st) return st;
     if (!psi || !hpsi || !eig) return rs::fail(RS_EINVAL, "rs_subspace_diag: null pointer");
-    hipStream_t s = (hipStream_t)stream;
     const int N = nblk * B;
     const double dv = c->g->h * c->g->h * c->g->h;
     if ((st = rs::gram(c->w, psi, hpsi, c->g->np, B, nblk, dtype, prec, dv, c->A.as<double>(), 2, s))) return st;
-    if ((st = rs::eigh(c->w, c->A.as<double>(), c->V.as<double>(), eig, N, s))) return st;
+    if ((st = rs::eigh(c->w, c->A.as<double>(), c->V.as<double>(), eig, N, s, max_sweeps))) return st;
     if ((st = rs::rotate(c->w, psi, c->V.as<double>(), c->g->np, B, nblk, dtype, prec, nullptr, s))) return st;
     return rs::rotate(c->w, hpsi, c->V.as<double>(), c->g->np, B, nblk, dtype, prec, nullptr, s);
 }
+
+extern "C" rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_t nblk, int32_t B,
+                                      int32_t dtype, int32_t prec, void *stream) {
+    return subspace_diag_capped(c, psi, hpsi, eig, nblk, B, dtype, prec, 30, (hipStream_t)stream);
+}
+

@@ -30,6 +30,13 @@ __device__ __forceinline__ float bf16_to_f(unsigned short h) {
     return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
+// Sum over the 64 lanes of a wave in a fixed butterfly order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Address of state j at point p in the block layout [j / B][p][j % B].
 __device__ __forceinline__ int64_t bidx(int64_t np, int B, int64_t p, int j) {
     return (int64_t)(j / B) * np * B + p * B + (j % B);
@@ -41,6 +48,7 @@ __device__ __forceinline__ int64_t bidx(int64_t np, int B, int64_t p, int j) {
 // MFMA A and B fragments of a TN product both read 16 consecutive states of
 // one point, so LDS reads are conflict-free.
 constexpr int KC64 = 16;
+constexpr size_t kJacobiLds = 136 * 1024;   // dynamic LDS for the Jacobi matrix (N <= 130)
 constexpr int MAXB = 16;    // 16x16 blocks per wave
 
 template <bool SYRK>
@@ -98,7 +106,8 @@ gram_f64_kernel(const double *__restrict__ X, const double *__restrict__ Y, int6
 
 // ---------------------------------------------------------- Gram BF16x3
 // FP32 data split as hi + lo (bfloat16 each); a.b ~ hi.hi + hi.lo + lo.hi
-// with FP32 accumulation on MFMA 16x16x32, plus lo.lo: on a diagonal entry
+// summed on MFMA 16x16x32 per 32-point stage and accumulated in FP64, plus
+// lo.lo: on a diagonal entry
 // (a sum of squares) the dropped lo.lo terms are all positive and would bias
 // the norms by ~1e-6 relative.  Staged as [state][point] so each lane's 8
 // consecutive points (its k-slice) are one 16-byte LDS read.
@@ -119,9 +128,9 @@ gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int
     const int64_t p_beg = (int64_t)chunk * CP;
     const int64_t p_end = min<int64_t>(np, p_beg + CP);
     const int b0 = split * bps, b1 = min(nblocks, b0 + bps);
-    f4 acc[MAXB];
+    d4 acc[MAXB];
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) acc[i] = f4{0, 0, 0, 0};
+    for (int i = 0; i < MAXB; ++i) acc[i] = d4{0, 0, 0, 0};
     for (int64_t p0 = p_beg; p0 < p_end; p0 += KCB) {
         for (int e = tid; e < KCB * N16; e += 256) {
             const int p = e / N16, j = e % N16;
@@ -150,10 +159,15 @@ gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int
                 const bf8 al = __builtin_bit_cast(bf8, *(const us8 *)(xl + ra));
                 const bf8 bh = __builtin_bit_cast(bf8, *(const us8 *)(yh + rb));
                 const bf8 bl = __builtin_bit_cast(bf8, *(const us8 *)(yl + rb));
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl, acc[i], 0, 0, 0);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[i], 0, 0, 0);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[i], 0, 0, 0);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[i], 0, 0, 0);
+                // the 32-point products of one stage are summed in FP32 on the
+                // matrix core and added to an FP64 accumulator, so rounding of
+                // long FP32 sums of same-sign terms cannot bias the result
+                f4 t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl, f4{0, 0, 0, 0}, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, t, 0, 0, 0);
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, t, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][r] += (double)t[r];
             }
         }
         __syncthreads();
@@ -166,35 +180,36 @@ gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int
             const int2 blk = blocks[bb];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[(int64_t)(blk.x * 16 + 4 * (lane / 16) + r) * N16 + blk.y * 16 + lane % 16] =
-                    (double)acc[i][r];
+                out[(int64_t)(blk.x * 16 + 4 * (lane / 16) + r) * N16 + blk.y * 16 + lane % 16] = acc[i][r];
         }
     }
 }
 
-// Fixed-order FP64 sum of the chunk partials; SYRK mirrors the upper blocks,
-// SYM symmetrises (M + M^T)/2.  Output S [N][N] = dv * sum.
+// Fixed-order FP64 sum of the chunk partials, one wave per output entry;
+// SYRK (mode 1) mirrors the upper blocks, mode 2 symmetrises (M + M^T)/2.
+// Output S [N][N] = dv * sum.
 __global__ void __launch_bounds__(256)
 gram_reduce_kernel(const double *__restrict__ partial, int nchunks, int N, int N16, int mode,
                    double dv, double *__restrict__ S) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (idx >= N * N) return;
     const int i = idx / N, j = idx % N;
     auto sum = [&](int a, int b) {
         double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += partial[((int64_t)c * N16 + a) * N16 + b];
-        return s;
+        for (int c = lane; c < nchunks; c += 64) s += partial[((int64_t)c * N16 + a) * N16 + b];
+        return wave_sum(s);
     };
     double v;
-    if (mode == 1) {                 // SYRK: only blocks with row block <= col block exist
-        const int a = i / 16 <= j / 16 ? i : j, b = i / 16 <= j / 16 ? j : i;
-        v = sum(a, b);
-    } else if (mode == 2) {          // symmetrised general product
+    if (mode == 1) {
+        const bool up = i / 16 <= j / 16;
+        v = sum(up ? i : j, up ? j : i);
+    } else if (mode == 2) {
         v = 0.5 * (sum(i, j) + sum(j, i));
     } else {
         v = sum(i, j);
     }
-    S[idx] = dv * v;
+    if (lane == 0) S[idx] = dv * v;
 }
 
 // --------------------------------------------------------- rotation FP64
@@ -241,10 +256,13 @@ rotate_f64_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64
 }
 
 // ------------------------------------------------------- rotation BF16x3
-// FP32 psi split in two bfloat16 terms, X (transposed) in three: xt0/1/2
-// [c][n].  The error of a two-term split of X would scale whole states by a
-// common factor (1 + O(2^-17)); with three terms it is O(2^-24).  Products
-// a_hi x_0 + a_hi x_1 + a_hi x_2 + a_lo x_0 + a_lo x_1 on MFMA bf16 16x16x32:
+// FP32 psi and the FP64 matrix X (transposed: xt0/1/2 [c][n]) are both split
+// in three bfloat16 terms, a = a0 + a1 + a2, x = x0 + x1 + x2, and the six
+// products with a_i x_j, i + j <= 2, are summed on MFMA bf16 16x16x32 in FP32.
+// That keeps the rotated field at FP32 accuracy: with only two terms for the
+// field, its 2^-17 relative representation error is white noise that the
+// kinetic operator amplifies by ~1/h^2 on the next application, and with two
+// terms for X every state would be scaled by a common 1 + O(2^-17).
 // A = psi (16 points x 32 states, each lane 8 consecutive states of one
 // point), B = X (32 states x 16 columns).
 __global__ void __launch_bounds__(256)
@@ -261,28 +279,34 @@ rotate_bf16x3_kernel(float *__restrict__ psi, const unsigned short *__restrict__
     const int64_t pa = p0 + lane % 16;
     for (int k0 = 0; k0 < N32; k0 += 32) {
         const int kb = k0 + 8 * (lane / 16);
-        us8 ah, al;
+        us8 a0, a1, a2;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const float v = (pa < np && kb + t < N) ? psi[bidx(np, B, pa, kb + t)] : 0.0f;
-            const unsigned short h = bf16_rne(v);
-            ah[t] = h;
-            al[t] = bf16_rne(v - bf16_to_f(h));
+            const unsigned short h0 = bf16_rne(v);
+            const float r1 = v - bf16_to_f(h0);
+            const unsigned short h1 = bf16_rne(r1);
+            a0[t] = h0;
+            a1[t] = h1;
+            a2[t] = bf16_rne(r1 - bf16_to_f(h1));
         }
-        const bf8 a_h = __builtin_bit_cast(bf8, ah), a_l = __builtin_bit_cast(bf8, al);
+        const bf8 A0 = __builtin_bit_cast(bf8, a0), A1 = __builtin_bit_cast(bf8, a1),
+                  A2 = __builtin_bit_cast(bf8, a2);
 #pragma unroll
         for (int c = 0; c < MAXC64; ++c) {
             if (c < ncb) {
                 const int col = c * 16 + lane % 16;
                 const int64_t o = (int64_t)col * N32 + kb;
-                const bf8 b_h = __builtin_bit_cast(bf8, *(const us8 *)(xth + o));
-                const bf8 b_m = __builtin_bit_cast(bf8, *(const us8 *)(xtm + o));
-                const bf8 b_l = __builtin_bit_cast(bf8, *(const us8 *)(xtl + o));
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, b_m, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b_l, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b_m, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, b_h, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, b_h, acc[c], 0, 0, 0);
+                const bf8 X0 = __builtin_bit_cast(bf8, *(const us8 *)(xth + o));
+                const bf8 X1 = __builtin_bit_cast(bf8, *(const us8 *)(xtm + o));
+                const bf8 X2 = __builtin_bit_cast(bf8, *(const us8 *)(xtl + o));
+                // smallest terms first
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, X0, acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, X1, acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X2, acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, X0, acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X1, acc[c], 0, 0, 0);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X0, acc[c], 0, 0, 0);
             }
         }
     }
@@ -318,14 +342,18 @@ split_xt_kernel(const double *__restrict__ Xm, int N, int N16, int N32, unsigned
 }
 
 // ------------------------------------------------------------- Cholesky
-// S = U^T U, U upper with positive diagonal (right-looking, one work-group,
-// matrix in global memory W which is overwritten).  info = 0, or the 1-based
-// column whose pivot is not positive (nothing after it is computed).
+// S = U^T U, U upper with positive diagonal (right-looking, one work-group;
+// the working copy W lives in LDS when it fits, else in global memory).
+// info = 0, or the 1-based column whose pivot is not positive (nothing after
+// it is computed).
+template <bool LDSW>
 __global__ void __launch_bounds__(1024)
-cholesky_kernel(const double *__restrict__ S, double *__restrict__ W, double *__restrict__ U, int N,
+cholesky_kernel(const double *__restrict__ S, double *__restrict__ Wg, double *__restrict__ U, int N,
                 int *__restrict__ info) {
+    extern __shared__ double ldsW[];
     __shared__ double piv;
     __shared__ int bad;
+    double *W = LDSW ? ldsW : Wg;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int e = tid; e < N * N; e += nt) {
         W[e] = S[e];
@@ -341,37 +369,54 @@ cholesky_kernel(const double *__restrict__ S, double *__restrict__ W, double *__
             } else {
                 piv = sqrt(d);
                 U[k * N + k] = piv;
+                W[k * N + k] = piv;
             }
         }
         __syncthreads();
         if (bad) break;
         const double inv = 1.0 / piv;
-        for (int j = k + 1 + tid; j < N; j += nt) U[k * N + j] = W[k * N + j] * inv;
+        for (int j = k + 1 + tid; j < N; j += nt) {
+            const double u = W[k * N + j] * inv;
+            W[k * N + j] = u;          // row k of W now holds row k of U
+            U[k * N + j] = u;
+        }
         __syncthreads();
         // trailing update of the upper triangle: W[i][j] -= U[k][i] U[k][j]
         const int m = N - k - 1;
         for (int e = tid; e < m * m; e += nt) {
             const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j >= i) W[i * N + j] -= U[k * N + i] * U[k * N + j];
+            if (j >= i) W[i * N + j] -= W[k * N + i] * W[k * N + j];
         }
         __syncthreads();
     }
     if (tid == 0) *info = bad;
 }
 
-// Inverse of an upper-triangular U (column j solved by thread j by back
-// substitution); T = U^-1 is upper triangular.  Skipped when info != 0.
-__global__ void __launch_bounds__(256)
+// Inverse of an upper-triangular U: one wave per column j solves U t = e_j
+// by back substitution, the inner products split over the 64 lanes and
+// summed in a fixed order; the column is kept in LDS.  T = U^-1 is upper
+// triangular.  Skipped when info != 0.
+__global__ void __launch_bounds__(1024)
 trinv_kernel(const double *__restrict__ U, double *__restrict__ T, int N, const int *__restrict__ info) {
+    __shared__ double col[16][256];
     if (*info) return;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        for (int i = N - 1; i > j; --i) T[i * N + j] = 0.0;
-        T[j * N + j] = 1.0 / U[j * N + j];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double *t = col[wave];
+    for (int j = wave; j < N; j += nw) {
+        for (int i = lane; i < N; i += 64) t[i] = 0.0;
+        if (lane == 0) t[j] = 1.0 / U[j * N + j];
+        __builtin_amdgcn_wave_barrier();
         for (int i = j - 1; i >= 0; --i) {
             double s = 0.0;
-            for (int k = i + 1; k <= j; ++k) s += U[i * N + k] * T[k * N + j];
-            T[i * N + j] = -s / U[i * N + i];
+            for (int k = i + 1 + lane; k <= j; k += 64) s += U[i * N + k] * t[k];
+            s = wave_sum(s);
+            if (lane == 0) t[i] = -s / U[i * N + i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        for (int i = lane; i < N; i += 64) T[i * N + j] = t[i];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -379,55 +424,63 @@ trinv_kernel(const double *__restrict__ U, double *__restrict__ T, int N, const 
 // Cyclic parallel Jacobi on a symmetric A (N <= 256, FP64, one work-group).
 // Each round rotates N/2 disjoint pairs (round-robin ordering) as
 // A <- J^T A J, V <- V J; sweeps repeat until the off-diagonal norm is below
-// tol * ||A||_F.  Eigenvalues ascending; each eigenvector's largest-magnitude
-// component is made positive.
+// tol * ||A||_F or max_sweeps is reached.  A lives in LDS when it fits
+// (LDSA), else in global memory.  Eigenvalues ascending; each eigenvector's
+// largest-magnitude component is made positive.
+template <bool LDSA>
 __global__ void __launch_bounds__(1024)
-jacobi_kernel(double *__restrict__ A, double *__restrict__ V, double *__restrict__ evals, int N,
-              int max_sweeps, double tol, int *__restrict__ sweeps_out, double *__restrict__ tmp) {
-    __shared__ double cs[256], sn[256];
-    __shared__ int pp[256], qq[256];
-    __shared__ double red[1024];
+jacobi_kernel(double *__restrict__ Ag, double *__restrict__ V, double *__restrict__ evals, int N,
+              int max_sweeps, double tol, int *__restrict__ sweeps_out, double *__restrict__ Vt) {
+    // A lives in LDS with an odd row stride (column accesses spread over
+    // the banks) when it fits, else in place in global memory.  The
+    // eigenvector matrix is accumulated transposed (Vt, rows contiguous) so
+    // that both passes of a round touch rows only.
+    extern __shared__ double ldsA[];
+    __shared__ double cs[128], sn[128];
+    __shared__ int pp[128], qq[128];
+    __shared__ double red[16];
     __shared__ int stop;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int ld = LDSA ? N + 1 : N;
+    double *A = LDSA ? ldsA : Ag;
+    if (LDSA)
+        for (int i = wave; i < N; i += nw)
+            for (int j = lane; j < N; j += 64) A[i * ld + j] = Ag[i * N + j];
+    for (int i = wave; i < N; i += nw)
+        for (int j = lane; j < N; j += 64) Vt[i * N + j] = i == j ? 1.0 : 0.0;
     const int M = N + (N & 1);        // even number of players (a dummy when N is odd)
-    for (int e = tid; e < N * N; e += nt) V[e] = (e / N == e % N) ? 1.0 : 0.0;
-    // ||A||_F
-    double loc = 0.0;
-    for (int e = tid; e < N * N; e += nt) loc += A[e] * A[e];
-    red[tid] = loc;
     __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
+    // Frobenius norms (all entries, then off-diagonal) in a fixed order
+    auto block_sum = [&](bool offdiag) {
+        double loc = 0.0;
+        for (int i = wave; i < N; i += nw)
+            for (int j = lane; j < N; j += 64)
+                if (!offdiag || i != j) loc += A[i * ld + j] * A[i * ld + j];
+        loc = wave_sum(loc);
+        if (lane == 0) red[wave] = loc;
         __syncthreads();
-    }
-    const double fro = sqrt(red[0]);
-    __syncthreads();
+        double t = 0.0;
+        for (int w2 = 0; w2 < nw; ++w2) t += red[w2];
+        __syncthreads();
+        return t;
+    };
+    const double fro = sqrt(block_sum(false));
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
-        // off-diagonal norm
-        loc = 0.0;
-        for (int e = tid; e < N * N; e += nt)
-            if (e / N != e % N) loc += A[e] * A[e];
-        red[tid] = loc;
-        __syncthreads();
-        for (int s = nt / 2; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        if (tid == 0) stop = !(sqrt(red[0]) > tol * fro);
+        const double off = sqrt(block_sum(true));
+        if (tid == 0) stop = !(off > tol * fro);
         __syncthreads();
         if (stop) break;
         for (int r = 0; r < M - 1; ++r) {
-            // pairs of this round, and their rotations
-            for (int k = tid; k < M / 2; k += nt) {
+            for (int k = tid; k < M / 2; k += blockDim.x) {
                 auto pos = [&](int i) { return i == 0 ? 0 : ((i - 1 + r) % (M - 1)) + 1; };
                 int p = pos(k), q = pos(M - 1 - k);
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;
                 if (q < N) {
-                    const double apq = A[p * N + q];
+                    const double apq = A[p * ld + q];
                     if (apq != 0.0) {
-                        const double app = A[p * N + p], aqq = A[q * N + q];
+                        const double app = A[p * ld + p], aqq = A[q * ld + q];
                         const double th = (aqq - app) / (2.0 * apq);
                         const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
@@ -437,59 +490,59 @@ jacobi_kernel(double *__restrict__ A, double *__restrict__ V, double *__restrict
                 pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
             }
             __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int e = tid; e < (M / 2) * N; e += nt) {
-                const int k = e / N, row = e % N;
+            // columns: A <- A J ; rows of Vt: Vt <- J^T Vt
+            for (int k = wave; k < M / 2; k += nw) {
                 const int p = pp[k], q = qq[k];
                 if (q >= N) continue;
                 const double c = cs[k], s = sn[k];
-                const double ap = A[row * N + p], aq = A[row * N + q];
-                A[row * N + p] = c * ap - s * aq;
-                A[row * N + q] = s * ap + c * aq;
-                const double vp = V[row * N + p], vq = V[row * N + q];
-                V[row * N + p] = c * vp - s * vq;
-                V[row * N + q] = s * vp + c * vq;
+                for (int i = lane; i < N; i += 64) {
+                    const double ap = A[i * ld + p], aq = A[i * ld + q];
+                    A[i * ld + p] = c * ap - s * aq;
+                    A[i * ld + q] = s * ap + c * aq;
+                    const double vp = Vt[p * N + i], vq = Vt[q * N + i];
+                    Vt[p * N + i] = c * vp - s * vq;
+                    Vt[q * N + i] = s * vp + c * vq;
+                }
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int e = tid; e < (M / 2) * N; e += nt) {
-                const int k = e / N, col = e % N;
+            // rows: A <- J^T A, and the annihilated pivots set exactly to 0
+            for (int k = wave; k < M / 2; k += nw) {
                 const int p = pp[k], q = qq[k];
                 if (q >= N) continue;
                 const double c = cs[k], s = sn[k];
-                const double ap = A[p * N + col], aq = A[q * N + col];
-                A[p * N + col] = c * ap - s * aq;
-                A[q * N + col] = s * ap + c * aq;
-            }
-            __syncthreads();
-            for (int k = tid; k < M / 2; k += nt) {
-                const int p = pp[k], q = qq[k];
-                if (q < N) {
-                    A[p * N + q] = 0.0;
-                    A[q * N + p] = 0.0;
+                for (int j = lane; j < N; j += 64) {
+                    const double ap = A[p * ld + j], aq = A[q * ld + j];
+                    A[p * ld + j] = j == q ? 0.0 : c * ap - s * aq;
+                    A[q * ld + j] = j == p ? 0.0 : s * ap + c * aq;
                 }
             }
             __syncthreads();
         }
     }
-    // sort ascending (rank by value, ties by index), normalise signs
-    for (int j = tid; j < N; j += nt) {
-        const double d = A[j * N + j];
+    // sort ascending (rank by value, ties by index), normalise signs:
+    // one wave per eigenvector
+    for (int j = wave; j < N; j += nw) {
+        const double d = A[j * ld + j];
         int rank = 0;
-        for (int i = 0; i < N; ++i) {
-            const double e = A[i * N + i];
-            rank += (e < d) || (e == d && i < j);
-        }
-        evals[rank] = d;
-        double big = 0.0;
+        double big = -1.0;
         int arg = 0;
-        for (int i = 0; i < N; ++i)
-            if (fabs(V[i * N + j]) > big) { big = fabs(V[i * N + j]); arg = i; }
-        const double sg = V[arg * N + j] < 0 ? -1.0 : 1.0;
-        for (int i = 0; i < N; ++i) tmp[i * N + rank] = sg * V[i * N + j];
+        for (int i = lane; i < N; i += 64) {
+            const double e = A[i * ld + i];
+            rank += (e < d) || (e == d && i < j);
+            const double v = fabs(Vt[j * N + i]);
+            if (v > big) { big = v; arg = i; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            rank += __shfl_xor(rank, o, 64);
+            const double ob = __shfl_xor(big, o, 64);
+            const int oa = __shfl_xor(arg, o, 64);
+            if (ob > big || (ob == big && oa < arg)) { big = ob; arg = oa; }
+        }
+        if (lane == 0) evals[rank] = d;
+        const double sg = Vt[j * N + arg] < 0 ? -1.0 : 1.0;
+        for (int i = lane; i < N; i += 64) V[i * N + rank] = sg * Vt[j * N + i];
     }
-    __syncthreads();
-    for (int e = tid; e < N * N; e += nt) V[e] = tmp[e];
     if (tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
@@ -551,7 +604,7 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
     }
     RS_HIP(hipGetLastError());
     const int rmode = syrk ? 1 : mode;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, w.partial.as<double>(),
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((N * N + 3) / 4), dim3(256), 0, st, w.partial.as<double>(),
                        nchunks, N, N16, rmode, dv, S);
     RS_HIP(hipGetLastError());
     return RS_OK;
@@ -581,20 +634,43 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
 }
 
 rs_status cholesky(DenseWork &w, const double *S, double *U, int N, int *info_dev, hipStream_t st) {
-    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, st, S, w.mwork.as<double>(), U, N, info_dev);
+    const size_t lds = (size_t)N * N * sizeof(double);
+    if (lds <= kJacobiLds) {
+        if (!w.chol_lds_set) {
+            RS_HIP(hipFuncSetAttribute((const void *)cholesky_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds));
+            w.chol_lds_set = true;
+        }
+        hipLaunchKernelGGL(cholesky_kernel<true>, dim3(1), dim3(1024), lds, st, S, w.mwork.as<double>(), U, N,
+                           info_dev);
+    } else {
+        hipLaunchKernelGGL(cholesky_kernel<false>, dim3(1), dim3(1024), 0, st, S, w.mwork.as<double>(), U, N,
+                           info_dev);
+    }
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
 
 rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStream_t st) {
-    hipLaunchKernelGGL(trinv_kernel, dim3(1), dim3(256), 0, st, U, T, N, info_dev);
+    hipLaunchKernelGGL(trinv_kernel, dim3(1), dim3(1024), 0, st, U, T, N, info_dev);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
 
-rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st) {
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, st, A, V, evals, N, 30, 1e-15,
-                       w.sweeps.as<int>(), w.mwork.as<double>());
+rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st, int max_sweeps) {
+    const size_t lds = (size_t)N * (N + 1) * sizeof(double);
+    if (lds <= kJacobiLds) {
+        if (!w.jacobi_lds_set) {
+            RS_HIP(hipFuncSetAttribute((const void *)jacobi_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds));
+            w.jacobi_lds_set = true;
+        }
+        hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), lds, st, A, V, evals, N, max_sweeps, 1e-15,
+                           w.sweeps.as<int>(), w.mwork.as<double>());
+    } else {
+        hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, st, A, V, evals, N, max_sweeps, 1e-15,
+                           w.sweeps.as<int>(), w.mwork.as<double>());
+    }
     RS_HIP(hipGetLastError());
     return RS_OK;
 }

@@ -19,6 +19,7 @@ struct DenseWork {
     DevBuf mwork;                      // double [N][N] scratch
     DevBuf xth, xtm, xtl;              // bfloat16 [N16][N32] three-term split rotation matrix
     DevBuf sweeps;                     // int
+    bool jacobi_lds_set = false, chol_lds_set = false;
 };
 
 rs_status dense_work_init(DenseWork &w, int64_t np, int max_states);
@@ -31,6 +32,9 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
                  int prec, const int *skip, hipStream_t st);
 rs_status cholesky(DenseWork &w, const double *S, double *U, int N, int *info_dev, hipStream_t st);
 rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStream_t st);
-rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st);
+// Jacobi eigensolver; max_sweeps bounds the work (30 reaches full FP64
+// accuracy from any start).
+rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st,
+               int max_sweeps = 30);
 
 }  // namespace rs

@@ -1,0 +1,559 @@
+// One RMM-DIIS eigensolver step on gfx950 (Secs. 3, 6 and 9).
+//
+// The step, for N states in nblk blocks of B (all on the caller's stream,
+// one host synchronisation at the end):
+//   1. H psi for all blocks; Rayleigh-Ritz (subspace matrix, Jacobi, rotate).
+//   2. Per state: eps0 = <psi|H psi>/<psi|psi>, R0 = H psi - eps0 psi,
+//      residual norm.  A block whose states are all below tol is frozen.
+//   3. d = K R0 (filter), H d; the trial step lambda minimises the Rayleigh
+//      quotient of psi + lambda d (2x2 generalised problem per state);
+//      psi1 = psi + lambda d, H psi1 = H psi + lambda H d.
+//   4. m - 1 DIIS iterations: residuals R_i = H psi_i - eps_i psi_i of the
+//      history; minimise |sum c R| / |sum c psi| over the history written in
+//      the basis {psi_L, psi_i - psi_L} (generalised eigenproblem per state,
+//      lowest eigenvector, c_0 = 1); psi_bar, H psi_bar, R_bar; d = K R_bar;
+//      psi_{j+1} = psi_bar + lambda d, H psi_{j+1} = H psi_bar + lambda H d.
+//   5. Orthonormalise (Cholesky, eq. 8).
+// Per-state inner products are sums over points with FP64 accumulation and
+// a fixed-order reduction over point chunks; the small per-state problems
+// are solved in FP64, one thread per state.
+#include <cmath>
+#include <cstring>
+
+#include "dense.hpp"
+#include "internal.hpp"
+
+rs_status subspace_diag_capped(rs_ctx *c, void *psi, void *hpsi, double *eig, int nblk, int B, int dtype,
+                               int prec, int max_sweeps, hipStream_t st);
+
+namespace rs {
+rs_status hpsi_apply(const rs_grid *g, const rs_nl *nl, const void *vloc, const void *psi, void *hpsi,
+                     int nblk, int B, int dtype, hipStream_t st);
+rs_status filter_apply(const rs_grid *g, double alpha, const void *r, void *out, int nblk, int B, int dtype,
+                       hipStream_t st);
+}
+
+namespace {
+
+constexpr int kMaxHist = 4;   // iterates kept (m <= 3)
+constexpr int kChunk = 2048;  // points per reduction chunk
+// Jacobi sweeps per Rayleigh-Ritz inside a step: the subspace matrix is
+// nearly diagonal once the states settle (then one or two sweeps reach full
+// accuracy); early on a partial diagonalisation is still a valid rotation.
+constexpr int kSweeps = 6;
+
+// --------------------------------------------------- per-state reductions
+// partial[k][chunk][col], col = blk * B + s.  One work-group per (chunk,
+// block); lanes: state s, rows r striding over the chunk's points.
+template <int K, typename Op>
+__global__ void __launch_bounds__(256)
+colreduce_kernel(Op op, int64_t np, int B, int nchunks, int N, double *__restrict__ partial) {
+    __shared__ double red[K][256];
+    const int blk = blockIdx.y, tid = threadIdx.x;
+    const int s = tid % B, r = tid / B, R = 256 / B;
+    const int64_t p0 = (int64_t)blockIdx.x * kChunk, p1 = min<int64_t>(np, p0 + kChunk);
+    const int col = blk * B + s;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int64_t p = p0 + r; p < p1; p += R) op((int64_t)blk * np * B + p * B + s, col, acc);
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int st = R / 2; st > 0; st >>= 1) {
+        if (r < st)
+#pragma unroll
+            for (int k = 0; k < K; ++k) red[k][tid] += red[k][tid + st * B];
+        __syncthreads();
+    }
+    if (r == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) partial[((int64_t)k * nchunks + blockIdx.x) * N + col] = red[k][s];
+}
+
+// One wave per output: lanes sum strided chunks, then a fixed butterfly.
+__global__ void __launch_bounds__(256)
+colreduce_final(const double *__restrict__ partial, int K, int nchunks, int N, double dv, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (idx >= K * N) return;
+    const int k = idx / N, c = idx % N;
+    double s = 0.0;
+    for (int ch = lane; ch < nchunks; ch += 64) s += partial[((int64_t)k * nchunks + ch) * N + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[idx] = dv * s;
+}
+
+template <typename T> struct OpDots2 {   // <x|x>, <x|y>
+    const T *x, *y;
+    __device__ void operator()(int64_t i, int, double *a) const {
+        const double u = x[i], v = y[i];
+        a[0] += u * u;
+        a[1] += u * v;
+    }
+};
+template <typename T> struct OpResid {   // R = h - eps x, <R|R>
+    const T *x, *h;
+    T *R;
+    const double *eps;
+    __device__ void operator()(int64_t i, int c, double *a) const {
+        const T r = (T)((double)h[i] - eps[c] * (double)x[i]);
+        R[i] = r;
+        a[0] += (double)r * (double)r;
+    }
+};
+template <typename T> struct OpLam {     // <x|Hd>, <d|Hx>, <d|Hd>, <x|d>, <d|d>
+    const T *x, *hx, *d, *hd;
+    __device__ void operator()(int64_t i, int, double *a) const {
+        const double u = x[i], hu = hx[i], v = d[i], hv = hd[i];
+        a[0] += u * hv;
+        a[1] += v * hu;
+        a[2] += v * hv;
+        a[3] += u * v;
+        a[4] += v * v;
+    }
+};
+// DIIS matrices over n = L + 1 iterates in the basis {x_L, x_i - x_L}:
+// A_ab = <r_a|r_b>, B_ab = <e_a|e_b> (upper triangles, 2 * n(n+1)/2 values)
+template <typename T, int NIT> struct OpDiis {
+    const T *x[NIT], *h[NIT];
+    const double *eps;   // [NIT][N]
+    int N;
+    __device__ void operator()(int64_t i, int c, double *a) const {
+        double e[NIT], r[NIT];
+        const double xl = x[NIT - 1][i];
+        const double rl = (double)h[NIT - 1][i] - eps[(NIT - 1) * N + c] * xl;
+        e[0] = xl;
+        r[0] = rl;
+#pragma unroll
+        for (int k = 0; k < NIT - 1; ++k) {
+            const double xk = x[k][i];
+            e[k + 1] = xk - xl;
+            r[k + 1] = ((double)h[k][i] - eps[k * N + c] * xk) - rl;
+        }
+        int t = 0;
+#pragma unroll
+        for (int p = 0; p < NIT; ++p)
+#pragma unroll
+            for (int q = p; q < NIT; ++q) {
+                a[t] += r[p] * r[q];
+                a[t + NIT * (NIT + 1) / 2] += e[p] * e[q];
+                ++t;
+            }
+    }
+};
+
+template <int K, typename Op>
+rs_status colreduce(const Op &op, int64_t np, int B, int nblk, double dv, double *partial, double *out,
+                    hipStream_t st) {
+    const int N = nblk * B;
+    const int nchunks = (int)((np + kChunk - 1) / kChunk);
+    hipLaunchKernelGGL((colreduce_kernel<K, Op>), dim3(nchunks, nblk), dim3(256), 0, st, op, np, B, nchunks, N,
+                       partial);
+    RS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(colreduce_final, dim3((K * N + 3) / 4), dim3(256), 0, st, partial, K, nchunks, N, dv,
+                       out);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+// --------------------------------------------------------- map kernels
+// y = x + lambda d, hy = hx + lambda hd (per-state lambda)
+template <typename T>
+__global__ void __launch_bounds__(256)
+axpy2_kernel(const T *__restrict__ x, const T *__restrict__ hx, const T *__restrict__ d, const T *__restrict__ hd,
+             T *__restrict__ y, T *__restrict__ hy, const double *__restrict__ lam, int64_t np, int B, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i / (np * B)) * B + (int)(i % B);
+    const double l = lam[c];
+    y[i] = (T)((double)x[i] + l * (double)d[i]);
+    hy[i] = (T)((double)hx[i] + l * (double)hd[i]);
+}
+
+// psi_bar = sum_a c_a e_a, H psi_bar = sum_a c_a he_a, R_bar = sum_a c_a r_a
+template <typename T> struct Hist {
+    const T *x[kMaxHist], *h[kMaxHist];
+};
+
+template <typename T, int NIT>
+__global__ void __launch_bounds__(256)
+combine_kernel(Hist<T> H, const double *__restrict__ eps, const double *__restrict__ coef, T *__restrict__ xb,
+               T *__restrict__ hb, T *__restrict__ rb, int64_t np, int B, int N, int64_t total) {
+    const T *const *xs = H.x;
+    const T *const *hs = H.h;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i / (np * B)) * B + (int)(i % B);
+    const double xl = xs[NIT - 1][i], hl = hs[NIT - 1][i];
+    const double rl = hl - eps[(NIT - 1) * N + c] * xl;
+    double sx = coef[c * kMaxHist] * xl, sh = coef[c * kMaxHist] * hl, sr = coef[c * kMaxHist] * rl;
+#pragma unroll
+    for (int k = 0; k < NIT - 1; ++k) {
+        const double ck = coef[c * kMaxHist + k + 1];
+        const double xk = xs[k][i], hk = hs[k][i];
+        sx += ck * (xk - xl);
+        sh += ck * (hk - hl);
+        sr += ck * ((hk - eps[k * N + c] * xk) - rl);
+    }
+    xb[i] = (T)sx;
+    hb[i] = (T)sh;
+    rb[i] = (T)sr;
+}
+
+// ----------------------------------------------------- per-state solvers
+// Lowest eigenpair of the symmetric generalised problem A c = mu B c
+// (n <= 4): scale by diag(B)^-1/2, Cholesky of B, Jacobi on L^-1 A L^-T.
+// Returns false when B is not positive definite.
+__device__ bool lowest_geneig(int n, const double *A_in, const double *B_in, double *c) {
+    double A[16], Bm[16], D[4], L[16], C[16], V[16];
+    for (int i = 0; i < n; ++i) {
+        if (!(B_in[i * n + i] > 0.0)) return false;
+        D[i] = 1.0 / sqrt(B_in[i * n + i]);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            A[i * n + j] = A_in[i * n + j] * D[i] * D[j];
+            Bm[i * n + j] = B_in[i * n + j] * D[i] * D[j];
+        }
+    for (int i = 0; i < 16; ++i) L[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double d = Bm[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0.0)) return false;
+        L[j * n + j] = sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double s = Bm[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / L[j * n + j];
+        }
+    }
+    // C = L^-1 A L^-T: solve L Y = A, then L C^T = Y^T
+    double Y[16];
+    for (int col = 0; col < n; ++col)
+        for (int i = 0; i < n; ++i) {
+            double s = A[i * n + col];
+            for (int k = 0; k < i; ++k) s -= L[i * n + k] * Y[k * n + col];
+            Y[i * n + col] = s / L[i * n + i];
+        }
+    for (int row = 0; row < n; ++row)
+        for (int i = 0; i < n; ++i) {
+            double s = Y[row * n + i];
+            for (int k = 0; k < i; ++k) s -= L[i * n + k] * C[row * n + k];
+            C[row * n + i] = s / L[i * n + i];
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            V[i * n + j] = i == j ? 1.0 : 0.0;
+            if (j > i) C[i * n + j] = C[j * n + i] = 0.5 * (C[i * n + j] + C[j * n + i]);
+        }
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += C[i * n + j] * C[i * n + j];
+                if (i != j) off += C[i * n + j] * C[i * n + j];
+            }
+        if (!(off > 1e-32 * tot)) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = C[p * n + q];
+                if (apq == 0.0) continue;
+                const double th = (C[q * n + q] - C[p * n + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {
+                    const double kp = C[k * n + p], kq = C[k * n + q];
+                    C[k * n + p] = cs * kp - sn * kq;
+                    C[k * n + q] = sn * kp + cs * kq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double pk = C[p * n + k], qk = C[q * n + k];
+                    C[p * n + k] = cs * pk - sn * qk;
+                    C[q * n + k] = sn * pk + cs * qk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double kp = V[k * n + p], kq = V[k * n + q];
+                    V[k * n + p] = cs * kp - sn * kq;
+                    V[k * n + q] = sn * kp + cs * kq;
+                }
+            }
+    }
+    int lo = 0;
+    for (int i = 1; i < n; ++i)
+        if (C[i * n + i] < C[lo * n + lo]) lo = i;
+    // c = D L^-T y
+    double y[4];
+    for (int i = 0; i < n; ++i) y[i] = V[i * n + lo];
+    for (int i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * c[k];
+        c[i] = s / L[i * n + i];
+    }
+    for (int i = 0; i < n; ++i) c[i] *= D[i];
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(c[i])) return false;
+    return true;
+}
+
+// Trial step lambda (state frozen -> 0).  dots: [<x|Hx>, <x|x>] and
+// [<x|Hd>, <d|Hx>, <d|Hd>, <x|d>, <d|d>].
+__global__ void lambda_kernel(const double *__restrict__ d2, const double *__restrict__ d5,
+                              const int *__restrict__ active, int N, double *__restrict__ lam) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double l = 0.0;
+    const double b22 = d5[4 * N + c];
+    if (active[c] && b22 > 0.0) {
+        const double s = 1.0 / sqrt(b22);
+        const double a11 = d2[1 * N + c], b11 = d2[0 * N + c];
+        const double a12 = 0.5 * (d5[0 * N + c] + d5[1 * N + c]) * s;
+        const double a22 = d5[2 * N + c] * s * s;
+        const double b12 = d5[3 * N + c] * s;
+        const double A[4] = {a11, a12, a12, a22}, Bm[4] = {b11, b12, b12, 1.0};
+        double v[2];
+        if (lowest_geneig(2, A, Bm, v) && v[0] != 0.0) l = v[1] / v[0] * s;
+    }
+    lam[c] = l;
+}
+
+// eps of the newest iterate from its dots [<x|x>, <x|Hx>]
+__global__ void eps_kernel(const double *__restrict__ d2, int N, double *__restrict__ eps_out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    eps_out[c] = d2[1 * N + c] / d2[0 * N + c];
+}
+
+// DIIS coefficients per state (c_0 = 1); frozen or degenerate -> e_0.
+__global__ void diis_kernel(const double *__restrict__ mats, int n, const double *__restrict__ lam, int N,
+                            double *__restrict__ coef) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double out[kMaxHist] = {1.0, 0.0, 0.0, 0.0};
+    if (lam[c] != 0.0) {
+        double A[16], Bm[16], v[4];
+        const int nt = n * (n + 1) / 2;
+        int t = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p; q < n; ++q) {
+                A[p * n + q] = A[q * n + p] = mats[(int64_t)t * N + c];
+                Bm[p * n + q] = Bm[q * n + p] = mats[(int64_t)(t + nt) * N + c];
+                ++t;
+            }
+        if (lowest_geneig(n, A, Bm, v) && v[0] != 0.0)
+            for (int i = 0; i < n; ++i) out[i] = v[i] / v[0];
+    }
+    for (int i = 0; i < kMaxHist; ++i) coef[c * kMaxHist + i] = out[i];
+}
+
+// eps0 = <x|Hx>/<x|x>; after the residual pass: res = sqrt(<R|R>), and a
+// block is active unless every state in it is below tol.
+__global__ void active_kernel(const double *__restrict__ rr, int N, int B, double tol, int block_stop,
+                              double *__restrict__ res, int *__restrict__ active) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    res[c] = sqrt(rr[c]);
+    int act = 1;
+    if (block_stop) {
+        const int b0 = (c / B) * B;
+        act = 0;
+        for (int k = b0; k < b0 + B; ++k) act |= !(sqrt(rr[k]) < tol);
+    }
+    active[c] = act;
+}
+
+}  // namespace
+
+struct rs_solver {
+    const rs_grid *g = nullptr;
+    const rs_nl *nl = nullptr;
+    const void *vloc = nullptr;
+    int N = 0, B = 0, nblk = 0, dtype = 0, prec = 0;
+    rs_solver_opts opts{};
+    rs_ctx *ctx = nullptr;
+    size_t field_bytes = 0;
+    rs::DevBuf hx[kMaxHist], hh[kMaxHist];  // history of iterates and H applied
+    rs::DevBuf R, d, hd, hpsi;
+    rs::DevBuf partial, d2, d5, rr, res, eig, lam, eps, mats, coef, active;
+    int steps = 0;
+};
+
+extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc, int32_t nstates,
+                                          int32_t B, int32_t dtype, const rs_solver_opts *opts, rs_solver **out) {
+    using namespace rs;
+    if (!g || !vloc || !out) return fail(RS_EINVAL, "rs_eigensolve_create: null argument");
+    *out = nullptr;
+    if (B < 1 || B > 64 || (B & (B - 1))) return fail(RS_EINVAL, "rs_eigensolve_create: bad B");
+    if (nstates < 1 || nstates % B || nstates > 256)
+        return fail(RS_EINVAL, "rs_eigensolve_create: nstates must be a multiple of B in [1, 256]");
+    if (dtype != RS_F64 && dtype != RS_F32) return fail(RS_EINVAL, "rs_eigensolve_create: bad dtype");
+    if (nl && nl->max_states < nstates) return fail(RS_EINVAL, "rs_eigensolve_create: projector set too small");
+    auto s = new (std::nothrow) rs_solver();
+    if (!s) return fail(RS_ENOMEM, "host allocation failed");
+    s->g = g;
+    s->nl = nl;
+    s->vloc = vloc;
+    s->N = nstates;
+    s->B = B;
+    s->nblk = nstates / B;
+    s->dtype = dtype;
+    s->prec = dtype == RS_F64 ? RS_PREC_NATIVE : RS_PREC_BF16X3;
+    rs_solver_opts o;
+    o.m = 3;
+    o.alpha = 0.5;
+    o.tol = 1e-6;
+    o.block_stop = 1;
+    if (opts) o = *opts;
+    if (o.m < 1 || o.m > kMaxHist - 1) { delete s; return fail(RS_EINVAL, "rs_eigensolve_create: m must be 1..3"); }
+    s->opts = o;
+    rs_status st = rs_ctx_create(g, nstates, &s->ctx);
+    if (st) { delete s; return st; }
+    const size_t es = dtype == RS_F64 ? 8 : 4;
+    s->field_bytes = (size_t)g->np * nstates * es;
+    const int N = nstates;
+    const int nchunks = (int)((g->np + kChunk - 1) / kChunk);
+    for (int i = 0; i <= o.m && !st; ++i) {   // iterate 0 is the caller's psi
+        if (i > 0) st = s->hx[i].alloc(s->field_bytes);
+        if (!st) st = s->hh[i].alloc(s->field_bytes);
+    }
+    if (!st) st = s->R.alloc(s->field_bytes);
+    if (!st) st = s->d.alloc(s->field_bytes);
+    if (!st) st = s->hd.alloc(s->field_bytes);
+    if (!st) st = s->partial.alloc(sizeof(double) * 12 * (size_t)nchunks * N);
+    if (!st) st = s->d2.alloc(sizeof(double) * 2 * N);
+    if (!st) st = s->d5.alloc(sizeof(double) * 5 * N);
+    if (!st) st = s->rr.alloc(sizeof(double) * N);
+    if (!st) st = s->res.alloc(sizeof(double) * N);
+    if (!st) st = s->eig.alloc(sizeof(double) * N);
+    if (!st) st = s->lam.alloc(sizeof(double) * N);
+    if (!st) st = s->eps.alloc(sizeof(double) * kMaxHist * N);
+    if (!st) st = s->mats.alloc(sizeof(double) * 12 * N);
+    if (!st) st = s->coef.alloc(sizeof(double) * kMaxHist * N);
+    if (!st) st = s->active.alloc(sizeof(int) * N);
+    if (st) {
+        rs_ctx_destroy(s->ctx);
+        delete s;
+        return st;
+    }
+    *out = s;
+    return RS_OK;
+}
+
+extern "C" void rs_eigensolve_destroy(rs_solver *s) {
+    if (!s) return;
+    rs_ctx_destroy(s->ctx);
+    delete s;
+}
+
+namespace {
+
+template <typename T>
+rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
+    using namespace rs;
+    const rs_grid *g = S->g;
+    const int64_t np = g->np;
+    const int B = S->B, nblk = S->nblk, N = S->N, m = S->opts.m;
+    const double dv = g->h * g->h * g->h;
+    const int64_t total = np * N;
+    const unsigned gm = (unsigned)((total + 255) / 256);
+    const unsigned gs = (unsigned)((N + 63) / 64);
+    T *h0 = S->hh[0].as<T>();
+    double *partial = S->partial.as<double>();
+    rs_status e;
+    // 1. H psi, Rayleigh-Ritz
+    if ((e = hpsi_apply(g, S->nl, S->vloc, psi, h0, nblk, B, S->dtype, st))) return e;
+    if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, kSweeps, st)))
+        return e;
+    // 2. eps0, residual, activity
+    if ((e = colreduce<2>(OpDots2<T>{psi, h0}, np, B, nblk, dv, partial, S->d2.as<double>(), st))) return e;
+    hipLaunchKernelGGL(eps_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N, S->eps.as<double>());
+    if ((e = colreduce<1>(OpResid<T>{psi, h0, S->R.as<T>(), S->eps.as<double>()}, np, B, nblk, dv, partial,
+                          S->rr.as<double>(), st)))
+        return e;
+    hipLaunchKernelGGL(active_kernel, dim3(gs), dim3(64), 0, st, S->rr.as<double>(), N, B, S->opts.tol,
+                       S->opts.block_stop, S->res.as<double>(), S->active.as<int>());
+    // 3. trial step
+    if ((e = filter_apply(g, S->opts.alpha, S->R.p, S->d.p, nblk, B, S->dtype, st))) return e;
+    if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
+    if ((e = colreduce<5>(OpLam<T>{psi, h0, S->d.as<T>(), S->hd.as<T>()}, np, B, nblk, dv, partial,
+                          S->d5.as<double>(), st)))
+        return e;
+    hipLaunchKernelGGL(lambda_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d5.as<double>(),
+                       S->active.as<int>(), N, S->lam.as<double>());
+    // history: iterate 0 is psi itself
+    const T *xs[kMaxHist], *hs[kMaxHist];
+    xs[0] = psi;
+    hs[0] = h0;
+    hipLaunchKernelGGL(axpy2_kernel<T>, dim3(gm), dim3(256), 0, st, psi, h0, S->d.as<T>(), S->hd.as<T>(),
+                       S->hx[1].as<T>(), S->hh[1].as<T>(), S->lam.as<double>(), np, B, total);
+    xs[1] = S->hx[1].as<T>();
+    hs[1] = S->hh[1].as<T>();
+    for (int n = 2; n <= m; ++n) {
+        // 4. DIIS iteration over the n iterates 0..n-1: eps of the newest
+        if ((e = colreduce<2>(OpDots2<T>{xs[n - 1], hs[n - 1]}, np, B, nblk, dv, partial, S->d2.as<double>(), st)))
+            return e;
+        hipLaunchKernelGGL(eps_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N,
+                           S->eps.as<double>() + (int64_t)(n - 1) * N);
+        if (n == 2) {
+            OpDiis<T, 2> op{{xs[0], xs[1]}, {hs[0], hs[1]}, S->eps.as<double>(), N};
+            if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
+        } else {
+            OpDiis<T, 3> op{{xs[0], xs[1], xs[2]}, {hs[0], hs[1], hs[2]}, S->eps.as<double>(), N};
+            if ((e = colreduce<12>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
+        }
+        hipLaunchKernelGGL(diis_kernel, dim3(gs), dim3(64), 0, st, S->mats.as<double>(), n, S->lam.as<double>(), N,
+                           S->coef.as<double>());
+        // psi_bar, H psi_bar into slot n; R_bar into R
+        T *xb = S->hx[n].as<T>(), *hb = S->hh[n].as<T>();
+        Hist<T> hist{};
+        for (int i = 0; i < n; ++i) {
+            hist.x[i] = xs[i];
+            hist.h[i] = hs[i];
+        }
+        if (n == 2)
+            hipLaunchKernelGGL((combine_kernel<T, 2>), dim3(gm), dim3(256), 0, st, hist, S->eps.as<double>(),
+                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, total);
+        else
+            hipLaunchKernelGGL((combine_kernel<T, 3>), dim3(gm), dim3(256), 0, st, hist, S->eps.as<double>(),
+                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, total);
+        RS_HIP(hipGetLastError());
+        if ((e = filter_apply(g, S->opts.alpha, S->R.p, S->d.p, nblk, B, S->dtype, st))) return e;
+        if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
+        hipLaunchKernelGGL(axpy2_kernel<T>, dim3(gm), dim3(256), 0, st, xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb,
+                           S->lam.as<double>(), np, B, total);
+        xs[n] = xb;
+        hs[n] = hb;
+    }
+    // newest iterate back into psi (frozen states: it equals psi)
+    RS_HIP(hipMemcpyAsync(psi, xs[m], S->field_bytes, hipMemcpyDeviceToDevice, st));
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+}  // namespace
+
+extern "C" rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, double *resnorm, int32_t *nconv,
+                                        void *stream) {
+    using namespace rs;
+    if (!s || !psi) return fail(RS_EINVAL, "rs_eigensolve_step: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    rs_status e = s->dtype == RS_F64 ? step_impl<double>(s, (double *)psi, st) : step_impl<float>(s, (float *)psi, st);
+    if (e) return e;
+    int32_t info = 0;
+    e = rs_orthonormalize_block(s->ctx, psi, s->nblk, s->B, s->dtype, s->prec, nullptr, &info, st);
+    std::vector<double> ev(s->N), rn(s->N);
+    RS_HIP(hipMemcpyAsync(ev.data(), s->eig.p, sizeof(double) * s->N, hipMemcpyDeviceToHost, st));
+    RS_HIP(hipMemcpyAsync(rn.data(), s->res.p, sizeof(double) * s->N, hipMemcpyDeviceToHost, st));
+    RS_HIP(hipStreamSynchronize(st));
+    if (eig) std::memcpy(eig, ev.data(), sizeof(double) * s->N);
+    if (resnorm) std::memcpy(resnorm, rn.data(), sizeof(double) * s->N);
+    int c = 0;
+    for (int k = 0; k < s->N; ++k) c += rn[k] < s->opts.tol;
+    if (nconv) *nconv = c;
+    for (int k = 0; k < s->N; ++k)
+        if (!std::isfinite(ev[k]) || !std::isfinite(rn[k]))
+            return fail(RS_ENONFINITE, "rs_eigensolve_step: non-finite eigenvalue or residual");
+    s->steps++;
+    return e;
+}

@@ -147,8 +147,8 @@ struct Slots {
 template <typename T, int ROW, int NZ, int Z0, bool FAST>
 __device__ __forceinline__ void
 hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t rp, rsrc_t rh,
-          uint32_t lane_off, const uint32_t *tbl, const T *__restrict__ vloc, T pre, T w0, T w1,
-          T w2, T w3, const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
+          uint32_t lane_off, const uint32_t *tbl, const T *__restrict__ vloc, T vconst, T pre, T w0,
+          T w1, T w2, T w3, const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
           const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
           const T *__restrict__ dpl, int dps) {
     constexpr int NP = 16 * NZ;
@@ -221,11 +221,11 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
 #pragma unroll
             for (int zz = 0; zz < NZ; ++zz) acc[(zz * 4 + y) * 4 + x] += lap[zz];
         }
-    // local potential
+    // local potential (or a constant when vloc is null)
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int q = Z0 * 16 + k;
-        const T vp = me.has(q) ? vloc[me.point(q)] : T(0);
+        const T vp = vloc == nullptr ? vconst : (me.has(q) ? vloc[me.point(q)] : T(0));
         acc[k] = pre * acc[k] + vp * own[k];
     }
     // non-local part 2, point-centric: sum over the atoms whose sphere holds
@@ -261,7 +261,7 @@ template <typename T, int B, int NZ, bool FAST>
 __global__ void __launch_bounds__(256)
 hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict__ exec,
                   int nexec, int nwg, int nwg_pad, const T *__restrict__ psi,
-                  T *__restrict__ hpsi, const T *__restrict__ vloc, int64_t np, int nblk,
+                  T *__restrict__ hpsi, const T *__restrict__ vloc, T vconst, int64_t np, int nblk,
                   T pre, T w0, T w1, T w2, T w3,
                   const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
                   const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
@@ -312,7 +312,7 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
     const int dps = 4 * B;
     const BrickRec br = bricks[b];
 #define RS_PART(ZZ)                                                                            \
-    hpsi_wave<T, ROW, NZ, ZZ, FAST>(br, bricks, b, rp, rh, lane_off, tbl, vloc, pre, w0, w1, w2, w3, \
+    hpsi_wave<T, ROW, NZ, ZZ, FAST>(br, bricks, b, rp, rh, lane_off, tbl, vloc, vconst, pre, w0, w1, w2, w3, \
                                     brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, dps)
     if (part == 0) RS_PART(0);
     if constexpr (PARTS >= 2) { if (part == 1) RS_PART(NZ); }
@@ -445,19 +445,21 @@ rs_status launch_project(const rs_grid *g, const rs_nl *nl, const T *psi, T *pro
     return RS_OK;
 }
 
+// Applies out = pre * L psi + V psi (+ V_nl psi when nl is given), L the
+// star stencil with first-difference weights w0..w3 (see line_lap); V is
+// vloc, or the constant vconst when vloc is null.
 template <typename T>
-rs_status launch_hpsi(const rs_grid *g, const rs_nl *nl, const T *vloc, const T *psi, T *hpsi,
-                      int nblk, int B, hipStream_t st) {
+rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vconst, const T *psi, T *hpsi,
+                         int nblk, int B, double pre_d, const double w[4], hipStream_t st) {
     if (g->nbricks == 0) return RS_OK;
     if ((uint64_t)g->np * 64 * sizeof(T) > kMaxField)
-        return fail(RS_ENOTSUP, "rs_hpsi_block: 64 state columns of the grid exceed 4 GiB");
+        return fail(RS_ENOTSUP, "stencil: 64 state columns of the grid exceed 4 GiB");
     const bool with_nl = nl != nullptr && nl->nat > 0;
     if (with_nl) {
         rs_status s = launch_project<T>(g, nl, psi, nullptr, nblk, B, st);
         if (s) return s;
     }
-    const double c1 = 8.0 / 5.0, c2 = -1.0 / 5.0, c3 = 8.0 / 315.0, c4 = -1.0 / 560.0;
-    const T pre = (T)(-0.5 / (g->h * g->h));
+    const T pre = (T)pre_d;
     const int ncg = (nblk * B + 63) / 64;
     const int32_t *bnl = with_nl ? nl->brick_nl.as<int32_t>() : nullptr;
     const int32_t *ptp = with_nl ? nl->pt_ptr.as<int32_t>() : nullptr;
@@ -465,9 +467,8 @@ rs_status launch_hpsi(const rs_grid *g, const rs_nl *nl, const T *vloc, const T 
     const T *egm = with_nl ? (sizeof(T) == 8 ? (const T *)nl->ent_gamma64.p : (const T *)nl->ent_gamma32.p) : nullptr;
     const T *dp = with_nl ? (const T *)nl->dp.p : nullptr;
     const int nat = with_nl ? nl->nat : 0;
-    const T w0 = (T)(c1 + c2 + c3 + c4), w1 = (T)(c2 + c3 + c4), w2 = (T)(c3 + c4), w3 = (T)c4;
-    // interior bricks: whole brick per wave in FP32, half in FP64; surface
-    // bricks: half (FP32) or a quarter (FP64) per wave
+    const T w0 = (T)w[0], w1 = (T)w[1], w2 = (T)w[2], w3 = (T)w[3];
+    // interior bricks: NZF planes per wave; surface bricks: NZS
     constexpr int NZF = sizeof(T) == 8 ? RS_NZF64 : RS_NZF32;
     constexpr int NZS = sizeof(T) == 8 ? 1 : 2;
     for (int pass = 0; pass < 2; ++pass) {
@@ -484,11 +485,13 @@ rs_status launch_hpsi(const rs_grid *g, const rs_nl *nl, const T *vloc, const T 
         if (fast)                                                                                  \
             hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZF, true>), grid, dim3(256), 0, st,     \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
-                               vloc, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, dp, nat); \
+                               vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
+                               dp, nat);                                                          \
         else                                                                                       \
             hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZS, false>), grid, dim3(256), 0, st,    \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
-                               vloc, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, dp, nat); \
+                               vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
+                               dp, nat);                                                          \
         break;
         switch (B) {
             RS_HPSI(1) RS_HPSI(2) RS_HPSI(4) RS_HPSI(8) RS_HPSI(16) RS_HPSI(32) RS_HPSI(64)
@@ -496,8 +499,17 @@ rs_status launch_hpsi(const rs_grid *g, const rs_nl *nl, const T *vloc, const T 
 #undef RS_HPSI
         RS_HIP(hipGetLastError());
     }
-    RS_HIP(hipGetLastError());
     return RS_OK;
+}
+
+// The 25-point kinetic stencil of Sec. 5.1: c = (8/5, -1/5, 8/315, -1/560),
+// W_j = sum_{m>j} c_m, prefactor -1/(2h^2).
+template <typename T>
+rs_status launch_hpsi(const rs_grid *g, const rs_nl *nl, const T *vloc, const T *psi, T *hpsi,
+                      int nblk, int B, hipStream_t st) {
+    const double c1 = 8.0 / 5.0, c2 = -1.0 / 5.0, c3 = 8.0 / 315.0, c4 = -1.0 / 560.0;
+    const double w[4] = {c1 + c2 + c3 + c4, c2 + c3 + c4, c3 + c4, c4};
+    return launch_stencil<T>(g, nl, vloc, T(0), psi, hpsi, nblk, B, -0.5 / (g->h * g->h), w, st);
 }
 
 rs_status check_fields(const rs_grid *g, const rs_nl *nl, int nblk, int B, int dtype,
@@ -563,3 +575,26 @@ extern "C" rs_status rs_apply_nl(const rs_grid *g, const rs_nl *nl, const void *
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
+
+namespace rs {
+
+rs_status hpsi_apply(const rs_grid *g, const rs_nl *nl, const void *vloc, const void *psi, void *hpsi,
+                     int nblk, int B, int dtype, hipStream_t st) {
+    if (dtype == RS_F64)
+        return launch_hpsi<double>(g, nl, (const double *)vloc, (const double *)psi, (double *)hpsi, nblk, B, st);
+    return launch_hpsi<float>(g, nl, (const float *)vloc, (const float *)psi, (float *)hpsi, nblk, B, st);
+}
+
+// Filter preconditioner: K r = alpha r + (1 - alpha)/6 (sum of the six nearest
+// neighbours) = r + (1 - alpha)/6 L7 r, L7 the 7-point second difference
+// (first-difference weights (1, 0, 0, 0)); zero outside the domain.
+rs_status filter_apply(const rs_grid *g, double alpha, const void *r, void *out, int nblk, int B, int dtype,
+                       hipStream_t st) {
+    const double w[4] = {1.0, 0.0, 0.0, 0.0};
+    const double pre = (1.0 - alpha) / 6.0;
+    if (dtype == RS_F64)
+        return launch_stencil<double>(g, nullptr, nullptr, 1.0, (const double *)r, (double *)out, nblk, B, pre, w, st);
+    return launch_stencil<float>(g, nullptr, nullptr, 1.0f, (const float *)r, (float *)out, nblk, B, pre, w, st);
+}
+
+}  // namespace rs

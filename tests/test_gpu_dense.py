@@ -115,7 +115,7 @@ def test_rotate(small, dtype, nblk, B):
     if dtype == np.float64:
         assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
     else:
-        bound = 2.0 ** -16 * np.abs(X.T) @ np.abs(x.astype(np.float64)) + 1e-6 * np.abs(want)
+        bound = 2.0 ** -21 * np.abs(X.T) @ np.abs(x.astype(np.float64)) + 2.0 ** -22 * np.abs(want)
         assert np.all(np.abs(got - want) <= bound)
 
 

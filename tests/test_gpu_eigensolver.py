@@ -1,0 +1,95 @@
+"""GPU eigensolver (RMM-DIIS step, filter, block stop) against the oracle's
+step, and converged eigenvalues against the exact discrete spectra."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import hamiltonian, linalg, rmmdiis
+
+torch = pytest.importorskip("torch")
+import paper_1306_2953_amd as rsd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+
+
+def _setup(w, N, B, dtype=np.float64, **kw):
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    nl = None
+    if atoms is not None:
+        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=N)
+    v = torch.from_numpy(H.vloc.astype(dtype)).to(DEV)
+    solver = rsd.Eigensolver(g, nl, v, N, B, **kw)
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), N, og.np)
+    psi, _, _ = linalg.orthonormalize(psi, og.dv)
+    return og, H, g, solver, psi
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_one_step_matches_oracle(m):
+    """The same step on the same orthonormal input: eigenvalues, residual norms
+    and the updated states agree with the oracle's implementation."""
+    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    N, B = 16, 8
+    og, H, g, solver, psi = _setup(w, N, B, m=m, tol=1e-12)
+    # a few oracle steps first so the states are not random noise
+    opts = rmmdiis.Options(m=m, block=B, tol=1e-12)
+    for _ in range(3):
+        psi = rmmdiis.rmmdiis_step(H, psi, opts)["psi"]
+    want = rmmdiis.rmmdiis_step(H, psi, opts)
+    t = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
+    eig, res, nconv = solver.step(t)
+    got = rsd.from_blocks(t.cpu().numpy())
+    assert np.max(np.abs(eig - want["eig"])) < 1e-10 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-8 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-7 * np.max(np.abs(want["psi"]))
+
+
+def test_block_stop_freezes_converged_blocks():
+    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    N, B = 16, 8
+    og, H, g, solver, psi = _setup(w, N, B, tol=1e9)
+    t = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
+    eig, res, nconv = solver.step(t)
+    assert nconv == N
+    lam, xi, p2, _ = linalg.rayleigh_ritz(psi, H.apply(psi), og.dv)
+    p2, _, _ = linalg.orthonormalize(p2, og.dv)
+    got = rsd.from_blocks(t.cpu().numpy())
+    assert np.max(np.abs(got - p2)) < 1e-9 * np.max(np.abs(p2))
+
+
+def test_converges_harmonic_box():
+    """Lowest four levels of the 32^3 harmonic box from random states."""
+    w = synthetic.make_config(1, nstates=4)
+    og, H, g, solver, psi = _setup(w, 4, 4, tol=1e-9)
+    t = torch.from_numpy(rsd.to_blocks(psi, 4)).to(DEV)
+    want = np.array([1.4999991750, 2.4999964915, 2.4999964915, 2.4999964915])
+    for it in range(150):
+        eig, res, nconv = solver.step(t)
+        if nconv == 4:
+            break
+    assert np.max(np.abs(eig - want)) < 1e-9
+    assert np.max(res) < 1e-9
+
+
+@pytest.mark.parametrize("dtype,etol", [(np.float64, 1e-10), (np.float32, 1e-6)])
+def test_converges_dense_bruteforce(dtype, etol):
+    """Tiny sphere with wells and projectors: lowest eigenvalues of the dense
+    matrix; the FP32 / split-precision solve reaches them to 1e-6 Ha."""
+    w = synthetic.make_config(2, radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
+    og, H, g, solver, psi = _setup(w, 8, 8, dtype=dtype, tol=1e-9 if dtype == np.float64 else 1e-5)
+    ev = np.linalg.eigvalsh(H.dense())[:8]
+    t = torch.from_numpy(rsd.to_blocks(psi.astype(dtype), 8)).to(DEV)
+    best = np.inf
+    for it in range(300):
+        eig, res, nconv = solver.step(t)
+        best = np.max(np.abs(eig - ev))
+        if best < etol / 10:
+            break
+    assert best < etol
