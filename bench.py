@@ -6,14 +6,21 @@ Kleinman-Bylander projectors) to all states of the workload, as blocks of B
 states, with inputs resident in HBM.  Prints one JSON line:
   value    = grid points x states per second of H psi (whole job),
   roofline = achieved HBM bandwidth of the stencil kernel (algorithmic bytes
-             per launch / average launch time, HIP events on its stream),
+             per launch / average launch time, HIP events on its stream);
+             traffic = HBM bytes per launch from the committed counter
+             summary when it was taken on the current stencil source,
+  eigensolve = time per RMM-DIIS step and time to 1e-6 Ha (lowest N-16
+             eigenvalues against a converged FP64 reference) for the plain
+             FP64 filter solve and the FP32 split-precision solve,
   cpu_baseline = the FP64 C/OpenMP oracle on the host cores (bounded sample).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3|5]
+                       [--no-eig] [--no-cpu] [--no-fp32]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -124,13 +131,102 @@ def cpu_baseline(w, budget_s=15.0):
         ch.hpsi_blocks(blk)
         reps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or reps >= 200:
+        if el > budget_s:
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=og.np * B * reps / el, unit="grid-pt*states/s", cores=threads,
                 kind="oracle",
                 sample=f"{reps} applications of FP64 H (stencil+V+KB) to one block of {B} "
                        f"states on the {og.np}-point grid, {el:.1f} s")
+
+
+def stencil_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1306_2953_amd", "csrc", "hpsi.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, dtype: str):
+    """HBM bytes per launch of the stencil kernel from the committed counter
+    summary, if it was taken on the current stencil source (else None)."""
+    path = os.path.join(ROOT, "profiles", "hpsi_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(f"{workload}/{dtype}")
+    if not e or e.get("source_sha256_16") != stencil_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every=20):
+    """Steps from the seeded start until the lowest N - nbuf states all have
+    residual < tol_res (or max_steps).  Returns per-step wall times, the
+    eigenvalue history and the time to |eps - ref| < 1e-6 on those states."""
+    import torch
+    import paper_1306_2953_amd as rsd
+    g = rsd.Grid.for_workload(w)
+    atoms = synthetic.draw_atoms(w) if w.nat else None
+    v = synthetic.potential_for(w, g.xyz(), atoms)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=w.nstates) if atoms is not None else None
+    npdt = np.float64 if dtype == "f64" else np.float32
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np).astype(npdt)
+    tp = torch.from_numpy(rsd.to_blocks(psi, B)).cuda()
+    del psi
+    tv = torch.from_numpy(v.astype(npdt)).cuda()
+    ctx = rsd.Context(g, w.nstates)
+    ctx.orthonormalize(tp)
+    solver = rsd.Eigensolver(g, nl, tv, w.nstates, B, tol=tol_res, block_stop=True)
+    keep = w.nstates - nbuf
+    times, eigs, t_hit, k_hit = [], [], None, None
+    elapsed = 0.0
+    for k in range(max_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eig, res, _ = solver.step(tp)
+        elapsed += time.perf_counter() - t0
+        times.append(elapsed)
+        eigs.append(eig.copy())
+        if ref is not None and t_hit is None and np.max(np.abs(eig[:keep] - ref[:keep])) < 1e-6:
+            t_hit, k_hit = elapsed, k + 1
+        if log_every and k % log_every == 0:
+            log(f"  {w.name} {dtype} step {k}: max res {res[:keep].max():.2e} eig0 {eig[0]:.10f} "
+                f"t {elapsed:.2f} s")
+        if np.all(res[:keep] < tol_res):
+            break
+    step_ms = 1e3 * (times[-1] - times[min(4, len(times) - 1)]) / max(1, len(times) - 1 - min(4, len(times) - 1))
+    del solver, ctx, tp
+    torch.cuda.empty_cache()
+    return dict(steps=len(times), eig=eigs[-1], eigs=eigs, times=times, t_hit=t_hit, k_hit=k_hit,
+                ms_per_step=step_ms, keep=keep)
+
+
+def eigensolve_compare(max_steps=600):
+    """Plain FP64 filter solve on the 128-state sphere (its converged end is
+    the reference) against the FP32 split-precision solve of the same system."""
+    w2, w3 = synthetic.CONFIGS[2], synthetic.CONFIGS[3]
+    log("eigensolve: FP64 reference / plain run")
+    r64 = eigensolve_run(w2, "f64", w2.block, max_steps, 1e-6)
+    ref = r64["eig"]
+    keep = r64["keep"]
+    t_hit = k_hit = None
+    for k, (t, e) in enumerate(zip(r64["times"], r64["eigs"])):
+        if np.max(np.abs(e[:keep] - ref[:keep])) < 1e-6:
+            t_hit, k_hit = t, k + 1
+            break
+    log("eigensolve: FP32 split-precision run")
+    r32 = eigensolve_run(w3, "f32", w3.block, max_steps, 1e-5, ref=ref)
+    err32 = float(np.max(np.abs(r32["eig"][:keep] - ref[:keep])))
+    return {
+        "metric": "time to |eps - eps_ref| < 1e-6 Ha on the lowest N-16 states",
+        "workload": w2.name, "states": w2.nstates, "measured_states": keep,
+        "reference": f"FP64 run converged to residual < 1e-6 on those states ({r64['steps']} steps)",
+        "plain_fp64_filter": {"time_s": t_hit, "steps": k_hit, "ms_per_step": r64["ms_per_step"]},
+        "fp32_split_filter": {"time_s": r32["t_hit"], "steps": r32["k_hit"],
+                              "ms_per_step": r32["ms_per_step"], "steps_run": r32["steps"],
+                              "final_max_eig_error_ha": err32},
+    }
 
 
 def main():
@@ -142,6 +238,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-eig", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -159,6 +256,10 @@ def main():
         log(f"fp32: {r3}")
         extra["cfg3_fp32"] = {k: r3[k] for k in ("ptstates_per_s", "gflops", "t_step",
                                                  "t_kernel", "achieved_gbs", "frac")}
+    eig = None
+    if a.config == 2 and not a.no_eig:
+        eig = eigensolve_compare()
+        log(f"eigensolve: {eig}")
     cpu = None
     if not a.no_cpu:
         log("cpu baseline")
@@ -177,10 +278,12 @@ def main():
                    "stencil_points": 25},
         "gflops": r["gflops"],
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": r["frac"], "traffic": None,
-                     "kernel": "hpsi_brick_kernel",
+                     "unit": "GB/s", "frac": r["frac"],
+                     "traffic": measured_traffic(w.name, dtype),
+                     "kernel": "hpsi_brick_kernel (interior + surface launches of one call)",
                      "bytes_per_launch": r["bytes_kernel"],
                      "avg_launch_s": r["t_kernel"]},
+        "eigensolve": eig,
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -49,6 +49,7 @@ typedef int rs_status;
 #define RS_EHIP        4  /* HIP runtime failure                           */
 #define RS_ENOMEM      5  /* device or host allocation failure             */
 #define RS_ENOTSUP     6  /* valid but unsupported combination             */
+#define RS_ENOTCONV    7  /* an iteration did not reach its tolerance      */
 
 #define RS_F64 0
 #define RS_F32 1
@@ -207,8 +208,9 @@ rs_status rs_rotate(rs_ctx *c, void *psi, const double *X, int32_t nblk, int32_t
 rs_status rs_cholesky(rs_ctx *c, const double *S, double *U, int32_t N, int32_t *info,
                       void *stream);
 
-/* Symmetric eigenproblem A V = V diag(evals) by cyclic Jacobi (FP64, DEVICE
- * arrays; A [N][N] is destroyed).  Eigenvalues ascending; column j of V is
+/* Symmetric eigenproblem A V = V diag(evals) by cyclic Jacobi in the
+ * parallel round-robin order (FP64, DEVICE arrays; A [N][N] must be exactly
+ * symmetric and is destroyed).  Eigenvalues ascending; column j of V is
  * eigenvector j with its largest-magnitude component positive.
  * Asynchronous. */
 rs_status rs_eigh(rs_ctx *c, double *A, double *V, double *evals, int32_t N, void *stream);
@@ -254,12 +256,14 @@ typedef struct {
     double  alpha;       /* filter centre weight (1/2)                       */
     double  tol;         /* residual threshold of the block stopping rule    */
     int32_t block_stop;  /* nonzero: freeze blocks whose states are all < tol */
+    int32_t record;      /* nonzero: keep R0 and sigma of each step for
+                            rs_eigensolve_residuals (training data)          */
 } rs_solver_opts;
 
 /* nstates (a multiple of B, <= 256) states of dtype on grid g with local
  * potential vloc (DEVICE [np] of dtype; must stay valid for the solver's
  * lifetime) and optional projectors nl.  opts NULL: m = 3, alpha = 1/2,
- * tol = 1e-6, block_stop = 1.  Allocates all workspaces (about 2(m+1)+3
+ * tol = 1e-6, block_stop = 1, record = 0.  Allocates all workspaces (about 2(m+1)+3
  * field arrays of np * nstates elements). */
 rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc,
                                int32_t nstates, int32_t B, int32_t dtype,
@@ -274,6 +278,96 @@ void rs_eigensolve_destroy(rs_solver *s);
  * RS_ENONFINITE if an eigenvalue or residual is not finite. */
 rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, double *resnorm,
                              int32_t *nconv, void *stream);
+
+/* ------------------------------------------- learned preconditioner
+ * Not from the paper: its RMM-DIIS step (Sec. 3) leaves the preconditioner
+ * open and uses a filter; this replaces the filter by a small network
+ * trained on the shifted kinetic problem.
+ *
+ * Network f: three 3x3x3 cross-correlation layers without bias, channels
+ * 1 -> 8 -> 8 -> 1, tanh after the first two; every layer's output is zero
+ * off the domain.  Preconditioner for a residual r of a state with shift
+ * sigma < 0:  K(r) = s g(sigma) f(r / s), s = rms of r over the grid points,
+ * g = softplus(a + b log(-sigma h^2)); K(0) = 0.  Parameters: one FP32
+ * vector of RS_CNN_NPARAM values, w1 [8][1][27], w2 [8][8][27],
+ * w3 [1][8][27] (weight layout [out][in][tap], tap t = 9 dz + 3 dy + dx
+ * reads the input at offset (dx-1, dy-1, dz-1)), then a, b.
+ * Network fields are dense boxes [n][Z][Y][X] (FP32, DEVICE, x fastest);
+ * on a grid the box is the smallest axis-aligned box holding every point,
+ * zero outside the domain, wrapped on periodic grids.  Network arithmetic
+ * is FP32. */
+#define RS_CNN_NPARAM 2162
+typedef struct rs_cnn rs_cnn;
+
+/* Scratch for batches of up to max_batch boxes of up to max_box points
+ * (max_batch * max_box <= 2^28); about 17 * 4 bytes per point for
+ * inference, twice that once training starts.  Parameters start at 0. */
+rs_status rs_cnn_create(int32_t max_batch, int64_t max_box, rs_cnn **out);
+void rs_cnn_destroy(rs_cnn *c);
+/* HOST float [RS_CNN_NPARAM]; setting also resets the Adam moments. */
+rs_status rs_cnn_set_params(rs_cnn *c, const float *params);
+rs_status rs_cnn_get_params(const rs_cnn *c, float *params);
+
+/* f = network(u) for n boxes of dims {Z, Y, X}, no mask (all points
+ * inside), zero outside the box or wrapped (periodic != 0).
+ * Asynchronous. */
+rs_status rs_cnn_forward(rs_cnn *c, const float *u, float *f, int32_t n,
+                         const int32_t dims[3], int32_t periodic, void *stream);
+
+/* Training loss and gradient on a batch of crops u (network input r/s),
+ * t (target x/s), shifts sigma (DEVICE double [n], < 0), zero outside each
+ * crop: loss = sum_i |g_i f(u_i) - t_i|^2 / sum_i |t_i|^2 over the points
+ * at least `margin` from the crop faces.  The gradient (all RS_CNN_NPARAM
+ * values, FP32 with FP64 sums over points) is kept for rs_cnn_adam_step and
+ * copied to grad (HOST, may be NULL); du (DEVICE [n][Z][Y][X], may be NULL)
+ * receives dloss/du.  Synchronises when loss or grad is given. */
+rs_status rs_cnn_loss_grad(rs_cnn *c, const float *u, const float *t, const double *sigma,
+                           int32_t n, const int32_t dims[3], double h, int32_t margin,
+                           double *loss, float *grad, float *du, void *stream);
+
+/* One Adam update (Kingma and Ba, 2015) of the parameters with the last
+ * gradient: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).  Asynchronous. */
+rs_status rs_cnn_adam_step(rs_cnn *c, float lr, float beta1, float beta2, float eps,
+                           void *stream);
+
+/* out = K(r) for fields r, out [nblk][np][B] of dtype (DEVICE, distinct);
+ * sigma DEVICE double [nblk*B].  The grid's box must fit max_box and B
+ * must not exceed max_batch.  Asynchronous. */
+rs_status rs_cnn_precondition(rs_cnn *c, const rs_grid *g, const void *r, const double *sigma,
+                              void *out, int32_t nblk, int32_t B, int32_t dtype, void *stream);
+
+/* Dims {Z, Y, X} of the grid's box. */
+rs_status rs_cnn_box(rs_cnn *c, const rs_grid *g, int32_t dims[3]);
+
+/* Training crops: for crop i with desc (HOST int32 [ncrops][4]) = (state k,
+ * box origin x0, y0, z0), u_i = r_k / s_k and t_i = x_k / s_k on the crop's
+ * points (dims cdims {Z, Y, X}), s_k the rms of r_k over the grid; zero off
+ * the domain, wrapped on periodic grids.  Synchronises. */
+rs_status rs_cnn_crops(rs_cnn *c, const rs_grid *g, const void *r, const void *x, int32_t nblk,
+                       int32_t B, int32_t dtype, int32_t ncrops, const int32_t *desc,
+                       const int32_t cdims[3], float *u_out, float *t_out, void *stream);
+
+/* Training targets: x_k = (T - sigma_k)^-1 r_k with T the kinetic stencil
+ * (Sec. 5.1) by conjugate gradients, each state to |r - (T - sigma) x| <=
+ * tol |r|; sigma DEVICE double [nblk*B], each < 0 (so T - sigma is positive
+ * definite).  r, x [nblk][np][B] of dtype, distinct.  Allocates its scratch
+ * (3 fields).  *iters (HOST, may be NULL) = iterations used.  Synchronises
+ * every 10 iterations.  RS_ENOTCONV if maxit is reached first. */
+rs_status rs_shifted_solve(const rs_grid *g, const void *r, const double *sigma, void *x,
+                           int32_t nblk, int32_t B, int32_t dtype, double tol, int32_t maxit,
+                           int32_t *iters, void *stream);
+
+/* Use the network as the solver's preconditioner (NULL: the filter).  Each
+ * step then also applies the kinetic stencil to psi for the shifts
+ * sigma_k = -<psi_k|T|psi_k>; a state whose <r|K r> is not positive and
+ * finite falls back to the filter.  The handle must outlive its use. */
+rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c);
+
+/* With opts.record: the last step's residuals R0 (after Rayleigh-Ritz) and
+ * shifts sigma_k = -<psi_k|T|psi_k> into R (DEVICE, the psi layout) and
+ * sigma (DEVICE double [nstates]).  Asynchronous. */
+rs_status rs_eigensolve_residuals(rs_solver *s, void *R, double *sigma, void *stream);
 
 #ifdef __cplusplus
 }

@@ -278,11 +278,15 @@ class Eigensolver:
     """RMM-DIIS eigensolver over the states of one grid (rs_solver)."""
 
     def __init__(self, grid: Grid, nl: Optional[NonLocal], vloc, nstates: int, B: int,
-                 m: int = 3, alpha: float = 0.5, tol: float = 1e-6, block_stop: bool = True):
+                 m: int = 3, alpha: float = 0.5, tol: float = 1e-6, block_stop: bool = True,
+                 record: bool = False):
         self.grid, self.nl, self.vloc = grid, nl, vloc     # vloc kept alive here
         self.nstates, self.B = nstates, B
+        self.dtype = vloc.dtype
+        self.precond = None
         o = _abi.SolverOpts()
         o.m, o.alpha, o.tol, o.block_stop = int(m), float(alpha), float(tol), int(block_stop)
+        o.record = int(record)
         self._h = ctypes.c_void_p()
         check(lib().rs_eigensolve_create(grid.handle, nl.handle if nl is not None else None,
                                          _dev(vloc, "vloc"), int(nstates), int(B),
@@ -301,12 +305,134 @@ class Eigensolver:
             res.ctypes.data_as(_abi.PF64), ctypes.byref(nconv), _stream(stream)))
         return eig, res, nconv.value
 
+    def set_precond(self, cnn: Optional["Cnn"]):
+        """Use the network as preconditioner (None: the filter)."""
+        check(lib().rs_eigensolve_set_precond(self._h, cnn.handle if cnn is not None else None))
+        self.precond = cnn          # kept alive while in use
+
+    def residuals(self, stream=None):
+        """(R0 [nblk, np, B], sigma [N]) of the last step (needs record=True)."""
+        torch = _torch()
+        R = torch.empty((self.nstates // self.B, self.grid.np, self.B), dtype=self.dtype, device="cuda")
+        sig = torch.empty(self.nstates, dtype=torch.float64, device="cuda")
+        check(lib().rs_eigensolve_residuals(self._h, _dev(R, "R"), _dev(sig, "sigma"), _stream(stream)))
+        return R, sig
+
     def __del__(self):
         h = getattr(self, "_h", None)
         L = getattr(_abi, "_lib", None) if _abi is not None else None
         if h and L is not None:
             L.rs_eigensolve_destroy(h)
             self._h = None
+
+
+class Cnn:
+    """Learned preconditioner network (rs_cnn): parameters, forward,
+    training loss/gradient, Adam, and application to grid fields."""
+
+    NPARAM = _abi.RS_CNN_NPARAM
+
+    def __init__(self, max_batch: int, max_box: int):
+        self._h = ctypes.c_void_p()
+        check(lib().rs_cnn_create(int(max_batch), int(max_box), ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (self.NPARAM,):
+            raise ValueError(f"params must have {self.NPARAM} values")
+        check(lib().rs_cnn_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.NPARAM, dtype=np.float32)
+        check(lib().rs_cnn_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    @staticmethod
+    def _dims(t):
+        if t.dim() != 4:
+            raise ValueError("boxes must be [n, Z, Y, X]")
+        return (ctypes.c_int32 * 3)(*[int(v) for v in t.shape[1:]])
+
+    def forward(self, u, periodic: bool = False, stream=None):
+        torch = _torch()
+        if u.dtype != torch.float32:
+            raise TypeError("network fields are float32")
+        f = torch.empty_like(u)
+        check(lib().rs_cnn_forward(self._h, _dev(u, "u"), _dev(f, "f"), int(u.shape[0]), self._dims(u),
+                                   int(periodic), _stream(stream)))
+        return f
+
+    def loss_grad(self, u, t, sigma, h: float, margin: int, want_du: bool = False, stream=None):
+        """Returns (loss, grad [NPARAM] float32, du or None)."""
+        torch = _torch()
+        loss = ctypes.c_double(0.0)
+        grad = np.empty(self.NPARAM, dtype=np.float32)
+        du = torch.empty_like(u) if want_du else None
+        check(lib().rs_cnn_loss_grad(self._h, _dev(u, "u"), _dev(t, "t"), _dev(sigma, "sigma"),
+                                     int(u.shape[0]), self._dims(u), float(h), int(margin),
+                                     ctypes.byref(loss), grad.ctypes.data_as(ctypes.c_void_p),
+                                     _dev(du, "du") if du is not None else None, _stream(stream)))
+        return loss.value, grad, du
+
+    def train_step(self, u, t, sigma, h: float, margin: int, lr: float, stream=None) -> float:
+        """Loss and gradient, then one Adam update; returns the loss."""
+        loss = ctypes.c_double(0.0)
+        check(lib().rs_cnn_loss_grad(self._h, _dev(u, "u"), _dev(t, "t"), _dev(sigma, "sigma"),
+                                     int(u.shape[0]), self._dims(u), float(h), int(margin),
+                                     ctypes.byref(loss), None, None, _stream(stream)))
+        self.adam_step(lr, stream=stream)
+        return loss.value
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                  stream=None):
+        check(lib().rs_cnn_adam_step(self._h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def box(self, grid: Grid):
+        d = (ctypes.c_int32 * 3)()
+        check(lib().rs_cnn_box(self._h, grid.handle, d))
+        return tuple(d)
+
+    def precondition(self, grid: Grid, r, sigma, stream=None):
+        nblk, B = _blocks(r, grid)
+        out = _torch().empty_like(r)
+        check(lib().rs_cnn_precondition(self._h, grid.handle, _dev(r, "r"), _dev(sigma, "sigma"),
+                                        _dev(out, "out"), nblk, B, _dtype_code(r), _stream(stream)))
+        return out
+
+    def crops(self, grid: Grid, r, x, desc: np.ndarray, dims, stream=None):
+        """desc [ncrops, 4] = (state, x0, y0, z0); returns (u, t) [ncrops, *dims]."""
+        torch = _torch()
+        nblk, B = _blocks(r, grid)
+        d = np.ascontiguousarray(desc, dtype=np.int32)
+        n = d.shape[0]
+        u = torch.empty((n,) + tuple(dims), dtype=torch.float32, device="cuda")
+        t = torch.empty_like(u)
+        cd = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+        check(lib().rs_cnn_crops(self._h, grid.handle, _dev(r, "r"), _dev(x, "x"), nblk, B, _dtype_code(r),
+                                 n, d.ctypes.data_as(ctypes.c_void_p), cd, _dev(u, "u"), _dev(t, "t"),
+                                 _stream(stream)))
+        return u, t
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_cnn_destroy(h)
+            self._h = None
+
+
+def shifted_solve(grid: Grid, r, sigma, tol: float = 1e-8, maxit: int = 2000, stream=None):
+    """x = (T - sigma)^-1 r per state by conjugate gradients; returns (x, iterations)."""
+    nblk, B = _blocks(r, grid)
+    x = _torch().empty_like(r)
+    it = ctypes.c_int32(0)
+    check(lib().rs_shifted_solve(grid.handle, _dev(r, "r"), _dev(sigma, "sigma"), _dev(x, "x"), nblk, B,
+                                 _dtype_code(r), float(tol), int(maxit), ctypes.byref(it), _stream(stream)))
+    return x, it.value
 
 
 def to_blocks(states: np.ndarray, B: int) -> np.ndarray:

@@ -11,7 +11,8 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsdft.so")
 
-RS_OK, RS_EINVAL, RS_ENOTPOSDEF, RS_ENONFINITE, RS_EHIP, RS_ENOMEM, RS_ENOTSUP = range(7)
+RS_OK, RS_EINVAL, RS_ENOTPOSDEF, RS_ENONFINITE, RS_EHIP, RS_ENOMEM, RS_ENOTSUP, RS_ENOTCONV = range(8)
+RS_CNN_NPARAM = 2162
 RS_F64, RS_F32 = 0, 1
 RS_PREC_NATIVE, RS_PREC_BF16X3 = 0, 1
 RS_GRID_BOX, RS_GRID_PERIODIC, RS_GRID_SPHERE = 0, 1, 2
@@ -27,7 +28,7 @@ PF64 = ctypes.POINTER(ctypes.c_double)
 
 
 class SolverOpts(ctypes.Structure):
-    _fields_ = [("m", I32), ("alpha", F64), ("tol", F64), ("block_stop", I32)]
+    _fields_ = [("m", I32), ("alpha", F64), ("tol", F64), ("block_stop", I32), ("record", I32)]
 
 
 class GridDesc(ctypes.Structure):
@@ -61,6 +62,19 @@ SIGNATURES = {
     "rs_eigensolve_create": (ctypes.c_int, [P, P, P, I32, I32, I32, P, ctypes.POINTER(P)]),
     "rs_eigensolve_destroy": (None, [P]),
     "rs_eigensolve_step": (ctypes.c_int, [P, P, PF64, PF64, PI32, P]),
+    "rs_eigensolve_set_precond": (ctypes.c_int, [P, P]),
+    "rs_eigensolve_residuals": (ctypes.c_int, [P, P, P, P]),
+    "rs_cnn_create": (ctypes.c_int, [I32, I64, ctypes.POINTER(P)]),
+    "rs_cnn_destroy": (None, [P]),
+    "rs_cnn_set_params": (ctypes.c_int, [P, P]),
+    "rs_cnn_get_params": (ctypes.c_int, [P, P]),
+    "rs_cnn_forward": (ctypes.c_int, [P, P, P, I32, PI32, I32, P]),
+    "rs_cnn_loss_grad": (ctypes.c_int, [P, P, P, P, I32, PI32, F64, I32, PF64, P, P, P]),
+    "rs_cnn_adam_step": (ctypes.c_int, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),
+    "rs_cnn_precondition": (ctypes.c_int, [P, P, P, P, P, I32, I32, I32, P]),
+    "rs_cnn_box": (ctypes.c_int, [P, P, PI32]),
+    "rs_cnn_crops": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P, PI32, P, P, P]),
+    "rs_shifted_solve": (ctypes.c_int, [P, P, P, P, I32, I32, I32, F64, I32, PI32, P]),
 }
 
 _lib = None

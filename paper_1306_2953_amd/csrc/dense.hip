@@ -8,6 +8,7 @@
 // The rotations psi' = psi X (eqs. (8), (10)) run point-parallel on matrix
 // cores, in place.  Cholesky, the triangular inverse and the Jacobi
 // eigensolver work on the small FP64 matrices inside one work-group.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -49,6 +50,7 @@ __device__ __forceinline__ int64_t bidx(int64_t np, int B, int64_t p, int j) {
 // one point, so LDS reads are conflict-free.
 constexpr int KC64 = 16;
 constexpr size_t kJacobiLds = 136 * 1024;   // dynamic LDS for the Jacobi matrix (N <= 130)
+constexpr int kMaxSweeps = 30;             // Jacobi sweep cap (rotation record size)
 constexpr int MAXB = 16;    // 16x16 blocks per wave
 
 template <bool SYRK>
@@ -213,46 +215,72 @@ gram_reduce_kernel(const double *__restrict__ partial, int nchunks, int N, int N
 }
 
 // --------------------------------------------------------- rotation FP64
-// psi'[p][c] = sum_n psi[p][n] X[n][c], in place.  One wave owns 16 points
-// and all N output columns, so every input it needs is read before the
-// first store.  MFMA f64 16x16x4: A = psi (16 points x 4 states),
-// B = X (4 states x 16 columns), output lane l, reg r -> point 4r + l/16.
-constexpr int MAXC64 = 16;   // 16-column blocks per wave (N <= 256)
-
-__global__ void __launch_bounds__(256)
-rotate_f64_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N,
-                  int ncb, const int *__restrict__ skip) {
+// psi'[p][c] = sum_n psi[p][n] X[n][c], in place.  MFMA f64 16x16x4:
+// A = psi (16 points x 4 states), B = X (4 states x 16 columns), output
+// lane l, reg r -> point 4r + l/16.
+constexpr int MAXC64 = 16;   // 16-column blocks (N <= 256)
+// A work-group of 8 waves owns 8 * 16 * MT points and all N <= 16 * MAXC
+// output columns, so every input it needs is read before the first store.
+// Rows of X arrive through LDS in chunks of KR rows shared by the 8 waves
+// (X is read once per work-group); MT point tiles per wave reuse each B
+// operand.
+constexpr int KR = 32;
+template <int MT, int MAXC>
+__global__ void __launch_bounds__(512)
+rotate_f64_lds_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N,
+                      int ncb, const int *__restrict__ skip) {
+    extern __shared__ double xs[];              // [KR][ncb * 16 + 4]
     if (skip && *skip) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (p0 >= np) return;
-    d4 acc[MAXC64];
+    const int ld = ncb * 16 + 4;
+    const int64_t pw = ((int64_t)blockIdx.x * 8 + wave) * 16 * MT;
+    d4 acc[MT][MAXC];
 #pragma unroll
-    for (int c = 0; c < MAXC64; ++c) acc[c] = d4{0, 0, 0, 0};
-    const int64_t pa = p0 + lane % 16;
-    for (int k0 = 0; k0 < N; k0 += 4) {
-        const int k = k0 + lane / 16;
-        const double a = (pa < np && k < N) ? psi[bidx(np, B, pa, k)] : 0.0;
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int c = 0; c < MAXC64; ++c) {
+        for (int c = 0; c < MAXC; ++c) acc[m][c] = d4{0, 0, 0, 0};
+    for (int kc = 0; kc < N; kc += KR) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < KR * ncb * 16; e += 512) {
+            const int r = e / (ncb * 16), col = e % (ncb * 16), k = kc + r;
+            xs[r * ld + col] = (k < N && col < N) ? Xm[(int64_t)k * N + col] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k4 = 0; k4 < KR; k4 += 4) {
+            const int k = kc + k4 + lane / 16;
+            double a[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int64_t pa = pw + m * 16 + lane % 16;
+                a[m] = (pa < np && k < N) ? psi[bidx(np, B, pa, k)] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                if (c < ncb) {
+                    const double b = xs[(k4 + lane / 16) * ld + c * 16 + lane % 16];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b, acc[m][c], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // every read of this work-group's points is done before the first store
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
             if (c < ncb) {
                 const int col = c * 16 + lane % 16;
-                const double b = (k < N && col < N) ? Xm[(int64_t)k * N + col] : 0.0;
-                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = pw + m * 16 + 4 * r + lane / 16;
+                    if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[m][c][r];
+                }
             }
         }
-    }
-#pragma unroll
-    for (int c = 0; c < MAXC64; ++c) {
-        if (c < ncb) {
-            const int col = c * 16 + lane % 16;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t p = p0 + 4 * r + lane / 16;
-                if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[c][r];
-            }
-        }
-    }
 }
 
 // ------------------------------------------------------- rotation BF16x3
@@ -264,63 +292,89 @@ rotate_f64_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64
 // kinetic operator amplifies by ~1/h^2 on the next application, and with two
 // terms for X every state would be scaled by a common 1 + O(2^-17).
 // A = psi (16 points x 32 states, each lane 8 consecutive states of one
-// point), B = X (32 states x 16 columns).
-__global__ void __launch_bounds__(256)
-rotate_bf16x3_kernel(float *__restrict__ psi, const unsigned short *__restrict__ xth,
-                     const unsigned short *__restrict__ xtl, const unsigned short *__restrict__ xtm,
-                     int64_t np, int B, int N, int N32, int ncb, const int *__restrict__ skip) {
+// point), B = X (32 states x 16 columns).  The three X terms are staged
+// through LDS, 32 rows at a time, shared by the 8 waves of a work-group
+// that owns 8 * 16 * MT points and all N <= 16 * MAXC columns (X is read
+// once per work-group, not per wave).
+constexpr int XLD = 40;    // LDS row of one column: 32 bf16 + 8 pad (80 bytes)
+template <int MT, int MAXC>
+__global__ void __launch_bounds__(512)
+rotate_bf16x3_lds_kernel(float *__restrict__ psi, const unsigned short *__restrict__ xth,
+                         const unsigned short *__restrict__ xtl, const unsigned short *__restrict__ xtm,
+                         int64_t np, int B, int N, int N32, int ncb, const int *__restrict__ skip) {
+    extern __shared__ unsigned short xl[];     // [3][ncb * 16][XLD]
     if (skip && *skip) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (p0 >= np) return;
-    f4 acc[MAXC64];
+    const int ncol = ncb * 16;
+    const int64_t pw = ((int64_t)blockIdx.x * 8 + wave) * 16 * MT;
+    f4 acc[MT][MAXC];
 #pragma unroll
-    for (int c = 0; c < MAXC64; ++c) acc[c] = f4{0, 0, 0, 0};
-    const int64_t pa = p0 + lane % 16;
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) acc[m][c] = f4{0, 0, 0, 0};
     for (int k0 = 0; k0 < N32; k0 += 32) {
-        const int kb = k0 + 8 * (lane / 16);
-        us8 a0, a1, a2;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const float v = (pa < np && kb + t < N) ? psi[bidx(np, B, pa, kb + t)] : 0.0f;
-            const unsigned short h0 = bf16_rne(v);
-            const float r1 = v - bf16_to_f(h0);
-            const unsigned short h1 = bf16_rne(r1);
-            a0[t] = h0;
-            a1[t] = h1;
-            a2[t] = bf16_rne(r1 - bf16_to_f(h1));
+        __syncthreads();
+        // 16-byte pieces: (term, column, quarter of the 32 rows)
+        for (int e = threadIdx.x; e < 3 * ncol * 4; e += 512) {
+            const int q = e & 3, col = (e >> 2) % ncol, term = (e >> 2) / ncol;
+            const unsigned short *src = term == 0 ? xth : (term == 1 ? xtm : xtl);
+            *(us8 *)(xl + (term * ncol + col) * XLD + 8 * q) = *(const us8 *)(src + (int64_t)col * N32 + k0 + 8 * q);
         }
-        const bf8 A0 = __builtin_bit_cast(bf8, a0), A1 = __builtin_bit_cast(bf8, a1),
-                  A2 = __builtin_bit_cast(bf8, a2);
+        __syncthreads();
+        const int kb = k0 + 8 * (lane / 16);
+        bf8 A0[MT], A1[MT], A2[MT];
 #pragma unroll
-        for (int c = 0; c < MAXC64; ++c) {
+        for (int m = 0; m < MT; ++m) {
+            const int64_t pa = pw + m * 16 + lane % 16;
+            us8 a0, a1, a2;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float v = (pa < np && kb + t < N) ? psi[bidx(np, B, pa, kb + t)] : 0.0f;
+                const unsigned short h0 = bf16_rne(v);
+                const float r1 = v - bf16_to_f(h0);
+                const unsigned short h1 = bf16_rne(r1);
+                a0[t] = h0;
+                a1[t] = h1;
+                a2[t] = bf16_rne(r1 - bf16_to_f(h1));
+            }
+            A0[m] = __builtin_bit_cast(bf8, a0);
+            A1[m] = __builtin_bit_cast(bf8, a1);
+            A2[m] = __builtin_bit_cast(bf8, a2);
+        }
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            if (c < ncb) {
+                const int o = (c * 16 + lane % 16) * XLD + 8 * (lane / 16);
+                const bf8 X0 = __builtin_bit_cast(bf8, *(const us8 *)(xl + o));
+                const bf8 X1 = __builtin_bit_cast(bf8, *(const us8 *)(xl + ncol * XLD + o));
+                const bf8 X2 = __builtin_bit_cast(bf8, *(const us8 *)(xl + 2 * ncol * XLD + o));
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    // smallest terms first
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[m], X0, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[m], X1, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], X2, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[m], X0, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], X1, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], X0, acc[m][c], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
             if (c < ncb) {
                 const int col = c * 16 + lane % 16;
-                const int64_t o = (int64_t)col * N32 + kb;
-                const bf8 X0 = __builtin_bit_cast(bf8, *(const us8 *)(xth + o));
-                const bf8 X1 = __builtin_bit_cast(bf8, *(const us8 *)(xtm + o));
-                const bf8 X2 = __builtin_bit_cast(bf8, *(const us8 *)(xtl + o));
-                // smallest terms first
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2, X0, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, X1, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X2, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, X0, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X1, acc[c], 0, 0, 0);
-                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, X0, acc[c], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = pw + m * 16 + 4 * (lane / 16) + r;
+                    if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[m][c][r];
+                }
             }
         }
-    }
-#pragma unroll
-    for (int c = 0; c < MAXC64; ++c) {
-        if (c < ncb) {
-            const int col = c * 16 + lane % 16;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t p = p0 + 4 * (lane / 16) + r;
-                if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[c][r];
-            }
-        }
-    }
 }
 
 // X [N][N] (FP64) -> transposed bfloat16 terms x0 + x1 + x2 [N16][N32]
@@ -427,14 +481,18 @@ trinv_kernel(const double *__restrict__ U, double *__restrict__ T, int N, const 
 // tol * ||A||_F or max_sweeps is reached.  A lives in LDS when it fits
 // (LDSA), else in global memory.  Eigenvalues ascending; each eigenvector's
 // largest-magnitude component is made positive.
+// Cyclic Jacobi in the parallel (round-robin) ordering: each round
+// annihilates M/2 disjoint pivots (p, q) at once, so A <- J^T A J splits
+// into independent 2x2 blocks (pair k) x (pair l).  One work-group; A lives
+// in LDS with an odd row stride when it fits, else in place in global
+// memory.  A must be symmetric; only blocks k <= l are computed and the
+// transposed block is mirrored, keeping A exactly symmetric.  The rotations
+// (c, s) are recorded per round for the eigenvector kernel; the final
+// diagonal goes to diag.
 template <bool LDSA>
 __global__ void __launch_bounds__(1024)
-jacobi_kernel(double *__restrict__ Ag, double *__restrict__ V, double *__restrict__ evals, int N,
-              int max_sweeps, double tol, int *__restrict__ sweeps_out, double *__restrict__ Vt) {
-    // A lives in LDS with an odd row stride (column accesses spread over
-    // the banks) when it fits, else in place in global memory.  The
-    // eigenvector matrix is accumulated transposed (Vt, rows contiguous) so
-    // that both passes of a round touch rows only.
+jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, int *__restrict__ sweeps_out,
+                  double2 *__restrict__ rot, double *__restrict__ diag) {
     extern __shared__ double ldsA[];
     __shared__ double cs[128], sn[128];
     __shared__ int pp[128], qq[128];
@@ -446,9 +504,8 @@ jacobi_kernel(double *__restrict__ Ag, double *__restrict__ V, double *__restric
     if (LDSA)
         for (int i = wave; i < N; i += nw)
             for (int j = lane; j < N; j += 64) A[i * ld + j] = Ag[i * N + j];
-    for (int i = wave; i < N; i += nw)
-        for (int j = lane; j < N; j += 64) Vt[i * N + j] = i == j ? 1.0 : 0.0;
     const int M = N + (N & 1);        // even number of players (a dummy when N is odd)
+    const int h = M / 2;
     __syncthreads();
     // Frobenius norms (all entries, then off-diagonal) in a fixed order
     auto block_sum = [&](bool offdiag) {
@@ -472,7 +529,7 @@ jacobi_kernel(double *__restrict__ Ag, double *__restrict__ V, double *__restric
         __syncthreads();
         if (stop) break;
         for (int r = 0; r < M - 1; ++r) {
-            for (int k = tid; k < M / 2; k += blockDim.x) {
+            for (int k = tid; k < h; k += blockDim.x) {
                 auto pos = [&](int i) { return i == 0 ? 0 : ((i - 1 + r) % (M - 1)) + 1; };
                 int p = pos(k), q = pos(M - 1 - k);
                 if (p > q) { const int t = p; p = q; q = t; }
@@ -488,48 +545,118 @@ jacobi_kernel(double *__restrict__ Ag, double *__restrict__ V, double *__restric
                     }
                 }
                 pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
+                rot[((int64_t)sweep * (M - 1) + r) * h + k] = make_double2(c, s);
             }
             __syncthreads();
-            // columns: A <- A J ; rows of Vt: Vt <- J^T Vt
-            for (int k = wave; k < M / 2; k += nw) {
-                const int p = pp[k], q = qq[k];
-                if (q >= N) continue;
-                const double c = cs[k], s = sn[k];
-                for (int i = lane; i < N; i += 64) {
-                    const double ap = A[i * ld + p], aq = A[i * ld + q];
-                    A[i * ld + p] = c * ap - s * aq;
-                    A[i * ld + q] = s * ap + c * aq;
-                    const double vp = Vt[p * N + i], vq = Vt[q * N + i];
-                    Vt[p * N + i] = c * vp - s * vq;
-                    Vt[q * N + i] = s * vp + c * vq;
-                }
-            }
-            __syncthreads();
-            // rows: A <- J^T A, and the annihilated pivots set exactly to 0
-            for (int k = wave; k < M / 2; k += nw) {
-                const int p = pp[k], q = qq[k];
-                if (q >= N) continue;
-                const double c = cs[k], s = sn[k];
-                for (int j = lane; j < N; j += 64) {
-                    const double ap = A[p * ld + j], aq = A[q * ld + j];
-                    A[p * ld + j] = j == q ? 0.0 : c * ap - s * aq;
-                    A[q * ld + j] = j == p ? 0.0 : s * ap + c * aq;
+            for (int k = wave; k < h; k += nw) {
+                const int pk = pp[k], qk = qq[k];
+                const bool vk = qk < N;
+                const double ck = cs[k], sk = sn[k];
+                for (int l = k + lane; l < h; l += 64) {
+                    const int pl = pp[l], ql = qq[l];
+                    const bool vl = ql < N;
+                    const double cl = cs[l], sl = sn[l];
+                    const double x00 = A[pk * ld + pl];
+                    const double x01 = vl ? A[pk * ld + ql] : 0.0;
+                    const double x10 = vk ? A[qk * ld + pl] : 0.0;
+                    const double x11 = vk && vl ? A[qk * ld + ql] : 0.0;
+                    // columns (A J), then rows (J^T A J)
+                    const double y00 = cl * x00 - sl * x01, y01 = sl * x00 + cl * x01;
+                    const double y10 = cl * x10 - sl * x11, y11 = sl * x10 + cl * x11;
+                    const double z00 = ck * y00 - sk * y10, z01 = ck * y01 - sk * y11;
+                    const double z10 = sk * y00 + ck * y10, z11 = sk * y01 + ck * y11;
+                    if (l == k) {
+                        // the pivot block: off-diagonal annihilated exactly
+                        A[pk * ld + pk] = z00;
+                        if (vk) {
+                            A[pk * ld + qk] = 0.0;
+                            A[qk * ld + pk] = 0.0;
+                            A[qk * ld + qk] = z11;
+                        }
+                        continue;
+                    }
+                    A[pk * ld + pl] = z00;
+                    A[pl * ld + pk] = z00;
+                    if (vl) {
+                        A[pk * ld + ql] = z01;
+                        A[ql * ld + pk] = z01;
+                    }
+                    if (vk) {
+                        A[qk * ld + pl] = z10;
+                        A[pl * ld + qk] = z10;
+                    }
+                    if (vk && vl) {
+                        A[qk * ld + ql] = z11;
+                        A[ql * ld + qk] = z11;
+                    }
                 }
             }
             __syncthreads();
         }
     }
-    // sort ascending (rank by value, ties by index), normalise signs:
-    // one wave per eigenvector
+    for (int i = tid; i < N; i += blockDim.x) diag[i] = A[i * ld + i];
+    if (tid == 0) *sweeps_out = sweep;
+}
+
+// Eigenvectors from the recorded rotations: V = J_1 J_2 ... J_R, and the
+// rows of V are independent (v <- v J per round), so one wave owns one row
+// in LDS and applies every round in order; rotations are staged through LDS
+// in groups of 16 rounds.
+constexpr int kRotStage = 16;
+__global__ void __launch_bounds__(256)
+jacobi_vec_kernel(const double2 *__restrict__ rot, const int *__restrict__ sweeps, int N, double *__restrict__ Vw) {
+    __shared__ double row[4][256];
+    __shared__ double2 stage[kRotStage][128];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = blockIdx.x * 4 + wave;
+    const int M = N + (N & 1), h = M / 2;
+    const int R = *sweeps * (M - 1);
+    if (i < N)
+        for (int j = lane; j < N; j += 64) row[wave][j] = i == j ? 1.0 : 0.0;
+    for (int r0 = 0; r0 < R; r0 += kRotStage) {
+        const int nr = min(kRotStage, R - r0);
+        __syncthreads();
+        for (int e = tid; e < nr * h; e += blockDim.x) stage[e / h][e % h] = rot[(int64_t)r0 * h + e];
+        __syncthreads();
+        if (i >= N) continue;
+        for (int t = 0; t < nr; ++t) {
+            const int r = (r0 + t) % (M - 1);
+            for (int k = lane; k < h; k += 64) {
+                auto pos = [&](int x) { return x == 0 ? 0 : ((x - 1 + r) % (M - 1)) + 1; };
+                int p = pos(k), q = pos(M - 1 - k);
+                if (p > q) { const int tt = p; p = q; q = tt; }
+                if (q >= N) continue;
+                const double c = stage[t][k].x, s = stage[t][k].y;
+                const double vp = row[wave][p], vq = row[wave][q];
+                row[wave][p] = c * vp - s * vq;
+                row[wave][q] = s * vp + c * vq;
+            }
+            // the next round reads entries other lanes of this wave wrote
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    if (i < N)
+        for (int j = lane; j < N; j += 64) Vw[(int64_t)i * N + j] = row[wave][j];
+}
+
+// Sort ascending (rank by value, ties by index) and normalise each
+// eigenvector's sign so that its largest-magnitude entry is positive
+// (ties: the lowest index); one wave per eigenvector.
+__global__ void __launch_bounds__(1024)
+jacobi_sort_kernel(const double *__restrict__ diag, const double *__restrict__ Vw, int N, double *__restrict__ V,
+                   double *__restrict__ evals) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int j = wave; j < N; j += nw) {
-        const double d = A[j * ld + j];
+        const double d = diag[j];
         int rank = 0;
         double big = -1.0;
         int arg = 0;
         for (int i = lane; i < N; i += 64) {
-            const double e = A[i * ld + i];
+            const double e = diag[i];
             rank += (e < d) || (e == d && i < j);
-            const double v = fabs(Vt[j * N + i]);
+            const double v = fabs(Vw[(int64_t)i * N + j]);
             if (v > big) { big = v; arg = i; }
         }
 #pragma unroll
@@ -540,10 +667,9 @@ jacobi_kernel(double *__restrict__ Ag, double *__restrict__ V, double *__restric
             if (ob > big || (ob == big && oa < arg)) { big = ob; arg = oa; }
         }
         if (lane == 0) evals[rank] = d;
-        const double sg = Vt[j * N + arg] < 0 ? -1.0 : 1.0;
-        for (int i = lane; i < N; i += 64) V[i * N + rank] = sg * Vt[j * N + i];
+        const double sg = Vw[(int64_t)arg * N + j] < 0 ? -1.0 : 1.0;
+        for (int i = lane; i < N; i += 64) V[(int64_t)i * N + rank] = sg * Vw[(int64_t)i * N + j];
     }
-    if (tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
 }  // namespace
@@ -577,7 +703,9 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
     const int nsplit = (nblocks + per_wg - 1) / per_wg;
     const int bps = (nblocks + nsplit - 1) / nsplit;
     const bool bf = dtype == RS_F32 && prec == RS_PREC_BF16X3;
-    int CP = bf ? 4096 : 2048;
+    // small chunks: several work-groups per compute unit (each owns all
+    // output blocks of its chunk), bounded by the partial-sum workspace
+    int CP = bf ? 1024 : 512;
     while ((np + CP - 1) / CP > w.max_chunks) CP *= 2;
     const int nchunks = (int)((np + CP - 1) / CP);
     if ((int64_t)nchunks * N16 * N16 * (int64_t)sizeof(double) > (int64_t)w.partial.bytes)
@@ -615,17 +743,31 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
     const int N = nblk * B;
     const int N16 = (N + 15) / 16 * 16;
     const int ncb = N16 / 16;
-    const unsigned nwg = (unsigned)((np + 63) / 64);
     if (dtype == RS_F64) {
-        hipLaunchKernelGGL(rotate_f64_kernel, dim3(nwg), dim3(256), 0, st, (double *)psi, Xm, np, B, N, ncb, skip);
+        const size_t lds = (size_t)KR * (ncb * 16 + 4) * sizeof(double);
+        if (ncb <= 8) {
+            const unsigned g2 = (unsigned)((np + 255) / 256);
+            hipLaunchKernelGGL((rotate_f64_lds_kernel<2, 8>), dim3(g2), dim3(512), lds, st, (double *)psi, Xm, np, B, N,
+                               ncb, skip);
+        } else {
+            const unsigned g1 = (unsigned)((np + 127) / 128);
+            hipLaunchKernelGGL((rotate_f64_lds_kernel<1, MAXC64>), dim3(g1), dim3(512), lds, st, (double *)psi, Xm, np, B, N,
+                               ncb, skip);
+        }
     } else if (prec == RS_PREC_BF16X3) {
         const int N32 = (N + 31) / 32 * 32;
         hipLaunchKernelGGL(split_xt_kernel, dim3((N16 * N32 + 255) / 256), dim3(256), 0, st, Xm, N, N16, N32,
                            w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(), w.xtm.as<unsigned short>());
         RS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(rotate_bf16x3_kernel, dim3(nwg), dim3(256), 0, st, (float *)psi,
-                           w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(), w.xtm.as<unsigned short>(),
-                           np, B, N, N32, ncb, skip);
+        const size_t lds = (size_t)3 * ncb * 16 * XLD * sizeof(unsigned short);
+        if (ncb <= 8)
+            hipLaunchKernelGGL((rotate_bf16x3_lds_kernel<2, 8>), dim3((unsigned)((np + 255) / 256)), dim3(512), lds,
+                               st, (float *)psi, w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(),
+                               w.xtm.as<unsigned short>(), np, B, N, N32, ncb, skip);
+        else
+            hipLaunchKernelGGL((rotate_bf16x3_lds_kernel<1, MAXC64>), dim3((unsigned)((np + 127) / 128)), dim3(512),
+                               lds, st, (float *)psi, w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(),
+                               w.xtm.as<unsigned short>(), np, B, N, N32, ncb, skip);
     } else {
         return fail(RS_ENOTSUP, "rotate: FP32 data needs RS_PREC_BF16X3");
     }
@@ -658,19 +800,27 @@ rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStrea
 }
 
 rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st, int max_sweeps) {
+    max_sweeps = std::max(0, std::min(max_sweeps, kMaxSweeps));
     const size_t lds = (size_t)N * (N + 1) * sizeof(double);
+    double *diag = w.diag.as<double>();
+    double2 *rot = w.rot.as<double2>();
     if (lds <= kJacobiLds) {
         if (!w.jacobi_lds_set) {
-            RS_HIP(hipFuncSetAttribute((const void *)jacobi_kernel<true>,
+            RS_HIP(hipFuncSetAttribute((const void *)jacobi_rot_kernel<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJacobiLds));
             w.jacobi_lds_set = true;
         }
-        hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), lds, st, A, V, evals, N, max_sweeps, 1e-15,
-                           w.sweeps.as<int>(), w.mwork.as<double>());
+        hipLaunchKernelGGL(jacobi_rot_kernel<true>, dim3(1), dim3(1024), lds, st, A, N, max_sweeps, 1e-15,
+                           w.sweeps.as<int>(), rot, diag);
     } else {
-        hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, st, A, V, evals, N, max_sweeps, 1e-15,
-                           w.sweeps.as<int>(), w.mwork.as<double>());
+        hipLaunchKernelGGL(jacobi_rot_kernel<false>, dim3(1), dim3(1024), 0, st, A, N, max_sweeps, 1e-15,
+                           w.sweeps.as<int>(), rot, diag);
     }
+    RS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(jacobi_vec_kernel, dim3((N + 3) / 4), dim3(256), 0, st, rot, w.sweeps.as<int>(), N,
+                       w.mwork.as<double>());
+    RS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(jacobi_sort_kernel, dim3(1), dim3(1024), 0, st, diag, w.mwork.as<double>(), N, V, evals);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -679,7 +829,8 @@ rs_status dense_work_init(DenseWork &w, int64_t np, int max_states) {
     const int N16 = (max_states + 15) / 16 * 16;
     const int N32 = (max_states + 31) / 32 * 32;
     w.max_states = max_states;
-    w.max_chunks = 512;
+    // chunk partials: at most 256 MiB
+    w.max_chunks = (int)std::max<int64_t>(64, std::min<int64_t>(4096, ((int64_t)256 << 20) / ((int64_t)N16 * N16 * 8)));
     rs_status s = RS_OK;
     const size_t nb16 = (size_t)(N16 / 16) * (N16 / 16);
     if (!s) s = w.partial.alloc((size_t)w.max_chunks * N16 * N16 * sizeof(double));
@@ -690,6 +841,9 @@ rs_status dense_work_init(DenseWork &w, int64_t np, int max_states) {
     if (!s) s = w.xtl.alloc((size_t)N16 * N32 * sizeof(unsigned short));
     if (!s) s = w.xtm.alloc((size_t)N16 * N32 * sizeof(unsigned short));
     if (!s) s = w.sweeps.alloc(sizeof(int));
+    if (!s) s = w.diag.alloc((size_t)max_states * sizeof(double));
+    const size_t M = max_states + (max_states & 1);
+    if (!s) s = w.rot.alloc((size_t)kMaxSweeps * (M - 1) * (M / 2) * sizeof(double2));
     (void)np;
     return s;
 }

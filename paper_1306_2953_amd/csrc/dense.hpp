@@ -11,7 +11,7 @@ namespace rs {
 // sized for max_states at creation (the field calls never allocate).
 struct DenseWork {
     int max_states = 0;
-    int max_chunks = 512;
+    int max_chunks = 512;               // set by dense_work_init
     DevBuf partial;                    // double [max_chunks][N16][N16]
     std::vector<int2> blocks_syrk, blocks_full;
     int blocks_n = 0;
@@ -19,6 +19,8 @@ struct DenseWork {
     DevBuf mwork;                      // double [N][N] scratch
     DevBuf xth, xtm, xtl;              // bfloat16 [N16][N32] three-term split rotation matrix
     DevBuf sweeps;                     // int
+    DevBuf diag;                       // double [N] Jacobi diagonal
+    DevBuf rot;                        // double2 [30][M-1][M/2] Jacobi rotations
     bool jacobi_lds_set = false, chol_lds_set = false;
 };
 
@@ -32,8 +34,8 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
                  int prec, const int *skip, hipStream_t st);
 rs_status cholesky(DenseWork &w, const double *S, double *U, int N, int *info_dev, hipStream_t st);
 rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStream_t st);
-// Jacobi eigensolver; max_sweeps bounds the work (30 reaches full FP64
-// accuracy from any start).
+// Jacobi eigensolver for a symmetric A (overwritten); max_sweeps (at most
+// 30) bounds the work (30 reaches full FP64 accuracy from any start).
 rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st,
                int max_sweeps = 30);
 

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "colreduce.hpp"
 #include "dense.hpp"
 #include "internal.hpp"
 
@@ -31,59 +32,20 @@ rs_status hpsi_apply(const rs_grid *g, const rs_nl *nl, const void *vloc, const 
                      int nblk, int B, int dtype, hipStream_t st);
 rs_status filter_apply(const rs_grid *g, double alpha, const void *r, void *out, int nblk, int B, int dtype,
                        hipStream_t st);
+rs_status kinetic_apply(const rs_grid *g, const void *psi, void *out, int nblk, int B, int dtype,
+                        hipStream_t st);
+rs_status cnn_precondition(rs_cnn *c, const rs_grid *g, const void *r, const double *sigma, void *out, int nblk,
+                           int B, int dtype, hipStream_t st);
 }
 
 namespace {
+using namespace rsred;
 
 constexpr int kMaxHist = 4;   // iterates kept (m <= 3)
-constexpr int kChunk = 2048;  // points per reduction chunk
 // Jacobi sweeps per Rayleigh-Ritz inside a step: the subspace matrix is
 // nearly diagonal once the states settle (then one or two sweeps reach full
 // accuracy); early on a partial diagonalisation is still a valid rotation.
 constexpr int kSweeps = 6;
-
-// --------------------------------------------------- per-state reductions
-// partial[k][chunk][col], col = blk * B + s.  One work-group per (chunk,
-// block); lanes: state s, rows r striding over the chunk's points.
-template <int K, typename Op>
-__global__ void __launch_bounds__(256)
-colreduce_kernel(Op op, int64_t np, int B, int nchunks, int N, double *__restrict__ partial) {
-    __shared__ double red[K][256];
-    const int blk = blockIdx.y, tid = threadIdx.x;
-    const int s = tid % B, r = tid / B, R = 256 / B;
-    const int64_t p0 = (int64_t)blockIdx.x * kChunk, p1 = min<int64_t>(np, p0 + kChunk);
-    const int col = blk * B + s;
-    double acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int64_t p = p0 + r; p < p1; p += R) op((int64_t)blk * np * B + p * B + s, col, acc);
-#pragma unroll
-    for (int k = 0; k < K; ++k) red[k][tid] = acc[k];
-    __syncthreads();
-    for (int st = R / 2; st > 0; st >>= 1) {
-        if (r < st)
-#pragma unroll
-            for (int k = 0; k < K; ++k) red[k][tid] += red[k][tid + st * B];
-        __syncthreads();
-    }
-    if (r == 0)
-#pragma unroll
-        for (int k = 0; k < K; ++k) partial[((int64_t)k * nchunks + blockIdx.x) * N + col] = red[k][s];
-}
-
-// One wave per output: lanes sum strided chunks, then a fixed butterfly.
-__global__ void __launch_bounds__(256)
-colreduce_final(const double *__restrict__ partial, int K, int nchunks, int N, double dv, double *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (idx >= K * N) return;
-    const int k = idx / N, c = idx % N;
-    double s = 0.0;
-    for (int ch = lane; ch < nchunks; ch += 64) s += partial[((int64_t)k * nchunks + ch) * N + c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) out[idx] = dv * s;
-}
 
 template <typename T> struct OpDots2 {   // <x|x>, <x|y>
     const T *x, *y;
@@ -143,20 +105,6 @@ template <typename T, int NIT> struct OpDiis {
             }
     }
 };
-
-template <int K, typename Op>
-rs_status colreduce(const Op &op, int64_t np, int B, int nblk, double dv, double *partial, double *out,
-                    hipStream_t st) {
-    const int N = nblk * B;
-    const int nchunks = (int)((np + kChunk - 1) / kChunk);
-    hipLaunchKernelGGL((colreduce_kernel<K, Op>), dim3(nchunks, nblk), dim3(256), 0, st, op, np, B, nchunks, N,
-                       partial);
-    RS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(colreduce_final, dim3((K * N + 3) / 4), dim3(256), 0, st, partial, K, nchunks, N, dv,
-                       out);
-    RS_HIP(hipGetLastError());
-    return RS_OK;
-}
 
 // --------------------------------------------------------- map kernels
 // y = x + lambda d, hy = hx + lambda hd (per-state lambda)
@@ -349,6 +297,26 @@ __global__ void diis_kernel(const double *__restrict__ mats, int n, const double
 
 // eps0 = <x|Hx>/<x|x>; after the residual pass: res = sqrt(<R|R>), and a
 // block is active unless every state in it is below tol.
+// sigma_k = -<psi_k|T psi_k> / <psi_k|psi_k>
+__global__ void sigma_kernel(const double *__restrict__ d2, int N, double *__restrict__ sigma) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    sigma[c] = -d2[1 * N + c] / d2[0 * N + c];
+}
+
+// Keep the learned direction d where <r|d> (rd[N + c]) is positive and
+// finite, else take the filter's alt.
+template <typename T>
+__global__ void __launch_bounds__(256)
+select_kernel(T *__restrict__ d, const T *__restrict__ alt, const double *__restrict__ rd, int64_t np, int B, int N,
+              int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int c = (int)(i / (np * B)) * B + (int)(i % B);
+    const double v = rd[N + c];
+    if (!(v > 0.0) || !isfinite(v)) d[i] = alt[i];
+}
+
 __global__ void active_kernel(const double *__restrict__ rr, int N, int B, double tol, int block_stop,
                               double *__restrict__ res, int *__restrict__ active) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,6 +344,8 @@ struct rs_solver {
     rs::DevBuf hx[kMaxHist], hh[kMaxHist];  // history of iterates and H applied
     rs::DevBuf R, d, hd, hpsi;
     rs::DevBuf partial, d2, d5, rr, res, eig, lam, eps, mats, coef, active;
+    rs::DevBuf sigma, R0, rd;    // shifts, recorded residuals, <r|K r>
+    rs_cnn *cnn = nullptr;
     int steps = 0;
 };
 
@@ -404,6 +374,7 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     o.alpha = 0.5;
     o.tol = 1e-6;
     o.block_stop = 1;
+    o.record = 0;
     if (opts) o = *opts;
     if (o.m < 1 || o.m > kMaxHist - 1) { delete s; return fail(RS_EINVAL, "rs_eigensolve_create: m must be 1..3"); }
     s->opts = o;
@@ -412,7 +383,7 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     const size_t es = dtype == RS_F64 ? 8 : 4;
     s->field_bytes = (size_t)g->np * nstates * es;
     const int N = nstates;
-    const int nchunks = (int)((g->np + kChunk - 1) / kChunk);
+    const int nchunks = (int)((g->np + rsred::kChunk - 1) / rsred::kChunk);
     for (int i = 0; i <= o.m && !st; ++i) {   // iterate 0 is the caller's psi
         if (i > 0) st = s->hx[i].alloc(s->field_bytes);
         if (!st) st = s->hh[i].alloc(s->field_bytes);
@@ -431,6 +402,9 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (!st) st = s->mats.alloc(sizeof(double) * 12 * N);
     if (!st) st = s->coef.alloc(sizeof(double) * kMaxHist * N);
     if (!st) st = s->active.alloc(sizeof(int) * N);
+    if (!st) st = s->sigma.alloc(sizeof(double) * N);
+    if (!st) st = s->rd.alloc(sizeof(double) * 2 * N);
+    if (!st && o.record) st = s->R0.alloc(s->field_bytes);
     if (st) {
         rs_ctx_destroy(s->ctx);
         delete s;
@@ -447,6 +421,26 @@ extern "C" void rs_eigensolve_destroy(rs_solver *s) {
 }
 
 namespace {
+
+// d = K r: the filter, or the network with a per-state fallback to the
+// filter (computed into alt, which the caller overwrites afterwards).
+template <typename T>
+rs_status precond(rs_solver *S, const T *r, T *d, T *alt, hipStream_t st) {
+    using namespace rs;
+    const rs_grid *g = S->g;
+    if (!S->cnn) return filter_apply(g, S->opts.alpha, r, d, S->nblk, S->B, S->dtype, st);
+    rs_status e;
+    if ((e = cnn_precondition(S->cnn, g, r, S->sigma.as<double>(), d, S->nblk, S->B, S->dtype, st))) return e;
+    if ((e = colreduce<2>(OpDots2<T>{r, d}, g->np, S->B, S->nblk, 1.0, S->partial.as<double>(), S->rd.as<double>(),
+                          st)))
+        return e;
+    if ((e = filter_apply(g, S->opts.alpha, r, alt, S->nblk, S->B, S->dtype, st))) return e;
+    const int64_t total = g->np * S->N;
+    hipLaunchKernelGGL(select_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, d, alt,
+                       S->rd.as<double>(), g->np, S->B, S->N, total);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
 
 template <typename T>
 rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
@@ -465,6 +459,13 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     if ((e = hpsi_apply(g, S->nl, S->vloc, psi, h0, nblk, B, S->dtype, st))) return e;
     if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, kSweeps, st)))
         return e;
+    // shifts for the learned preconditioner: sigma = -<psi|T psi>
+    if (S->cnn || S->opts.record) {
+        if ((e = kinetic_apply(g, psi, S->d.p, nblk, B, S->dtype, st))) return e;
+        if ((e = colreduce<2>(OpDots2<T>{psi, S->d.as<T>()}, np, B, nblk, dv, partial, S->d2.as<double>(), st)))
+            return e;
+        hipLaunchKernelGGL(sigma_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N, S->sigma.as<double>());
+    }
     // 2. eps0, residual, activity
     if ((e = colreduce<2>(OpDots2<T>{psi, h0}, np, B, nblk, dv, partial, S->d2.as<double>(), st))) return e;
     hipLaunchKernelGGL(eps_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N, S->eps.as<double>());
@@ -473,8 +474,9 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
         return e;
     hipLaunchKernelGGL(active_kernel, dim3(gs), dim3(64), 0, st, S->rr.as<double>(), N, B, S->opts.tol,
                        S->opts.block_stop, S->res.as<double>(), S->active.as<int>());
+    if (S->opts.record) RS_HIP(hipMemcpyAsync(S->R0.p, S->R.p, S->field_bytes, hipMemcpyDeviceToDevice, st));
     // 3. trial step
-    if ((e = filter_apply(g, S->opts.alpha, S->R.p, S->d.p, nblk, B, S->dtype, st))) return e;
+    if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
     if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
     if ((e = colreduce<5>(OpLam<T>{psi, h0, S->d.as<T>(), S->hd.as<T>()}, np, B, nblk, dv, partial,
                           S->d5.as<double>(), st)))
@@ -518,7 +520,7 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
             hipLaunchKernelGGL((combine_kernel<T, 3>), dim3(gm), dim3(256), 0, st, hist, S->eps.as<double>(),
                                S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, total);
         RS_HIP(hipGetLastError());
-        if ((e = filter_apply(g, S->opts.alpha, S->R.p, S->d.p, nblk, B, S->dtype, st))) return e;
+        if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
         if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
         hipLaunchKernelGGL(axpy2_kernel<T>, dim3(gm), dim3(256), 0, st, xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb,
                            S->lam.as<double>(), np, B, total);
@@ -556,4 +558,20 @@ extern "C" rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, do
             return fail(RS_ENONFINITE, "rs_eigensolve_step: non-finite eigenvalue or residual");
     s->steps++;
     return e;
+}
+
+extern "C" rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c) {
+    if (!s) return rs::fail(RS_EINVAL, "rs_eigensolve_set_precond: null solver");
+    s->cnn = c;
+    return RS_OK;
+}
+
+extern "C" rs_status rs_eigensolve_residuals(rs_solver *s, void *R, double *sigma, void *stream) {
+    if (!s || !R || !sigma) return rs::fail(RS_EINVAL, "rs_eigensolve_residuals: null argument");
+    if (!s->opts.record) return rs::fail(RS_EINVAL, "rs_eigensolve_residuals: the solver was created without record");
+    if (s->steps == 0) return rs::fail(RS_EINVAL, "rs_eigensolve_residuals: no step taken yet");
+    hipStream_t st = (hipStream_t)stream;
+    RS_HIP(hipMemcpyAsync(R, s->R0.p, s->field_bytes, hipMemcpyDeviceToDevice, st));
+    RS_HIP(hipMemcpyAsync(sigma, s->sigma.p, sizeof(double) * s->N, hipMemcpyDeviceToDevice, st));
+    return RS_OK;
 }

@@ -70,18 +70,23 @@ __device__ __forceinline__ T ld_slot(rsrc_t r, uint64_t mask, int start, int q, 
 // its outputs plus 8 operations per output.
 struct StencilW { double w0, w1, w2, w3; };
 
-template <typename T, int N>
+// R = 1 keeps only the nearest-neighbour term (the 7-point filter); the
+// values more than one step away are then never read.
+template <typename T, int N, int R>
 __device__ __forceinline__ void line_lap(const T (&v)[N], T (&lap)[N - 8], T w0, T w1, T w2, T w3) {
     T d[N - 1];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) d[k] = v[k + 1] - v[k];
+    for (int k = 0; k < N - 1; ++k)
+        if (R == 4 || (k >= 3 && k <= N - 5)) d[k] = v[k + 1] - v[k];
 #pragma unroll
     for (int i = 0; i < N - 8; ++i) {
         const int p = 4 + i;
         T t = w0 * (d[p] - d[p - 1]);
-        t += w1 * (d[p + 1] - d[p - 2]);
-        t += w2 * (d[p + 2] - d[p - 3]);
-        t += w3 * (d[p + 3] - d[p - 4]);
+        if constexpr (R == 4) {
+            t += w1 * (d[p + 1] - d[p - 2]);
+            t += w2 * (d[p + 2] - d[p - 3]);
+            t += w3 * (d[p + 3] - d[p - 4]);
+        }
         lap[i] = t;
     }
 }
@@ -139,12 +144,29 @@ struct Slots {
     }
 };
 
+// Phase fence: the accumulators are materialised (an empty asm that
+// reads and writes them) and the scheduler may not move instructions
+// across.  Without it the compiler defers all arithmetic to the end and
+// issues every load of the brick first, which needs several hundred
+// registers and leaves one wave per SIMD; with it each phase's loads are
+// consumed before the next phase's are issued.
+template <typename T, int N>
+__device__ __forceinline__ void phase_fence(T (&acc)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) asm volatile("" : "+v"(acc[k]));
+    __builtin_amdgcn_sched_barrier(0);
+}
+#define RS_PHASE() phase_fence(acc)
+#ifndef RS_PHASE_LINES
+#define RS_PHASE_LINES 2     // stencil lines per phase
+#endif
+
 // One wave computes NZ z-planes (from plane Z0) of one brick for 64 state
 // columns: lane l is state (c mod B) of block (c / B), c = 64*colgroup + l.
 // Everything that locates points (brick records, masks, offsets) is uniform
 // in the wave and lives in scalar registers; a lane's address is its column
 // offset plus the uniform slot offset.
-template <typename T, int ROW, int NZ, int Z0, bool FAST>
+template <typename T, int ROW, int NZ, int Z0, bool FAST, int R>
 __device__ __forceinline__ void
 hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t rp, rsrc_t rh,
           uint32_t lane_off, const uint32_t *tbl, const T *__restrict__ vloc, T vconst, T pre, T w0,
@@ -178,13 +200,14 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const int q = ((Z0 + zz) * 4 + y) * 4 + x;
-                v[x] = nb[0].load(rp, lane_off, q);
+                v[x] = (R == 4 || x == 3) ? nb[0].load(rp, lane_off, q) : T(0);
                 v[4 + x] = own[(zz * 4 + y) * 4 + x];
-                v[8 + x] = nb[1].load(rp, lane_off, q);
+                v[8 + x] = (R == 4 || x == 0) ? nb[1].load(rp, lane_off, q) : T(0);
             }
-            line_lap<T, 12>(v, lap, w0, w1, w2, w3);
+            line_lap<T, 12, R>(v, lap, w0, w1, w2, w3);
 #pragma unroll
             for (int x = 0; x < 4; ++x) acc[(zz * 4 + y) * 4 + x] = lap[x];
+            if ((zz * 4 + y) % RS_PHASE_LINES == RS_PHASE_LINES - 1) RS_PHASE();
         }
     // y lines
 #pragma unroll
@@ -195,13 +218,14 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
 #pragma unroll
             for (int y = 0; y < 4; ++y) {
                 const int q = ((Z0 + zz) * 4 + y) * 4 + x;
-                v[y] = nb[2].load(rp, lane_off, q);
+                v[y] = (R == 4 || y == 3) ? nb[2].load(rp, lane_off, q) : T(0);
                 v[4 + y] = own[(zz * 4 + y) * 4 + x];
-                v[8 + y] = nb[3].load(rp, lane_off, q);
+                v[8 + y] = (R == 4 || y == 0) ? nb[3].load(rp, lane_off, q) : T(0);
             }
-            line_lap<T, 12>(v, lap, w0, w1, w2, w3);
+            line_lap<T, 12, R>(v, lap, w0, w1, w2, w3);
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[(zz * 4 + y) * 4 + x] += lap[y];
+            if ((zz * 4 + x) % RS_PHASE_LINES == RS_PHASE_LINES - 1) RS_PHASE();
         }
     // z lines: NZ + 8 values around this wave's planes
 #pragma unroll
@@ -212,14 +236,16 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
 #pragma unroll
             for (int j = 0; j < NZ + 8; ++j) {
                 const int z = Z0 - 4 + j;
-                if (z < 0) v[j] = nb[4].load(rp, lane_off, ((z + 4) * 4 + y) * 4 + x);
+                if (R == 1 && (j < 3 || j > NZ + 4)) v[j] = T(0);
+                else if (z < 0) v[j] = nb[4].load(rp, lane_off, ((z + 4) * 4 + y) * 4 + x);
                 else if (z >= 4) v[j] = nb[5].load(rp, lane_off, ((z - 4) * 4 + y) * 4 + x);
                 else if (z >= Z0 && z < Z0 + NZ) v[j] = own[((z - Z0) * 4 + y) * 4 + x];
                 else v[j] = me.load(rp, lane_off, (z * 4 + y) * 4 + x);
             }
-            line_lap<T, NZ + 8>(v, lap, w0, w1, w2, w3);
+            line_lap<T, NZ + 8, R>(v, lap, w0, w1, w2, w3);
 #pragma unroll
             for (int zz = 0; zz < NZ; ++zz) acc[(zz * 4 + y) * 4 + x] += lap[zz];
+            if ((y * 4 + x) % RS_PHASE_LINES == RS_PHASE_LINES - 1) RS_PHASE();
         }
     // local potential (or a constant when vloc is null)
 #pragma unroll
@@ -257,7 +283,7 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
 // interior bricks, FAST, whose neighbours are all full, and the rest).  A
 // brick is split into 4/NZ parts of NZ z-planes, one wave each.  B is a
 // template parameter so that the row size B * sizeof(T) is a constant.
-template <typename T, int B, int NZ, bool FAST>
+template <typename T, int B, int NZ, bool FAST, int R>
 __global__ void __launch_bounds__(256)
 hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict__ exec,
                   int nexec, int nwg, int nwg_pad, const T *__restrict__ psi,
@@ -312,7 +338,7 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
     const int dps = 4 * B;
     const BrickRec br = bricks[b];
 #define RS_PART(ZZ)                                                                            \
-    hpsi_wave<T, ROW, NZ, ZZ, FAST>(br, bricks, b, rp, rh, lane_off, tbl, vloc, vconst, pre, w0, w1, w2, w3, \
+    hpsi_wave<T, ROW, NZ, ZZ, FAST, R>(br, bricks, b, rp, rh, lane_off, tbl, vloc, vconst, pre, w0, w1, w2, w3, \
                                     brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, dps)
     if (part == 0) RS_PART(0);
     if constexpr (PARTS >= 2) { if (part == 1) RS_PART(NZ); }
@@ -447,8 +473,9 @@ rs_status launch_project(const rs_grid *g, const rs_nl *nl, const T *psi, T *pro
 
 // Applies out = pre * L psi + V psi (+ V_nl psi when nl is given), L the
 // star stencil with first-difference weights w0..w3 (see line_lap); V is
-// vloc, or the constant vconst when vloc is null.
-template <typename T>
+// vloc, or the constant vconst when vloc is null.  R = 1: nearest
+// neighbours only (w1 = w2 = w3 = 0).
+template <typename T, int R = 4>
 rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vconst, const T *psi, T *hpsi,
                          int nblk, int B, double pre_d, const double w[4], hipStream_t st) {
     if (g->nbricks == 0) return RS_OK;
@@ -483,12 +510,12 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
 #define RS_HPSI(BB)                                                                                \
     case BB:                                                                                       \
         if (fast)                                                                                  \
-            hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZF, true>), grid, dim3(256), 0, st,     \
+            hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZF, true, R>), grid, dim3(256), 0, st,     \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
                                vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
                                dp, nat);                                                          \
         else                                                                                       \
-            hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZS, false>), grid, dim3(256), 0, st,    \
+            hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZS, false, R>), grid, dim3(256), 0, st,    \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
                                vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
                                dp, nat);                                                          \
@@ -593,8 +620,25 @@ rs_status filter_apply(const rs_grid *g, double alpha, const void *r, void *out,
     const double w[4] = {1.0, 0.0, 0.0, 0.0};
     const double pre = (1.0 - alpha) / 6.0;
     if (dtype == RS_F64)
-        return launch_stencil<double>(g, nullptr, nullptr, 1.0, (const double *)r, (double *)out, nblk, B, pre, w, st);
-    return launch_stencil<float>(g, nullptr, nullptr, 1.0f, (const float *)r, (float *)out, nblk, B, pre, w, st);
+        return launch_stencil<double, 1>(g, nullptr, nullptr, 1.0, (const double *)r, (double *)out, nblk, B, pre, w,
+                                         st);
+    return launch_stencil<float, 1>(g, nullptr, nullptr, 1.0f, (const float *)r, (float *)out, nblk, B, pre, w, st);
+}
+
+}  // namespace rs
+
+namespace rs {
+
+// Kinetic energy alone: out = T psi (the 25-point stencil, no potential).
+rs_status kinetic_apply(const rs_grid *g, const void *psi, void *out, int nblk, int B, int dtype,
+                        hipStream_t st) {
+    const double c1 = 8.0 / 5.0, c2 = -1.0 / 5.0, c3 = 8.0 / 315.0, c4 = -1.0 / 560.0;
+    const double w[4] = {c1 + c2 + c3 + c4, c2 + c3 + c4, c3 + c4, c4};
+    const double pre = -0.5 / (g->h * g->h);
+    if (dtype == RS_F64)
+        return launch_stencil<double>(g, nullptr, nullptr, 0.0, (const double *)psi, (double *)out, nblk, B, pre, w,
+                                      st);
+    return launch_stencil<float>(g, nullptr, nullptr, 0.0f, (const float *)psi, (float *)out, nblk, B, pre, w, st);
 }
 
 }  // namespace rs

@@ -1,0 +1,184 @@
+"""GPU parity of the learned preconditioner (network forward, training
+gradient, Adam, application on grids, training crops) and of the
+shifted-kinetic solves against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import cnn as ocnn
+from oracle import grid as ogrid
+from oracle import stencil
+
+torch = pytest.importorskip("torch")
+import paper_1306_2953_amd as rsd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+
+
+def _params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(scale=scale, size=ocnn.NP)
+    p[ocnn.NW], p[ocnn.NW + 1] = 0.3, -0.8
+    return p.astype(np.float32).astype(np.float64)   # exactly representable in FP32
+
+
+def _dev(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else a.astype(dtype))
+    return torch.from_numpy(a).to(DEV)
+
+
+def _rel(got, want):
+    return np.linalg.norm(np.ravel(got - want)) / np.linalg.norm(np.ravel(want))
+
+
+@pytest.mark.parametrize("dims,periodic", [((10, 12, 9), False), ((8, 8, 8), True), ((5, 3, 7), False)])
+def test_forward_matches_oracle(dims, periodic):
+    p = _params(1)
+    net = rsd.Cnn(4, 2048)
+    net.set_params(p)
+    assert np.array_equal(net.get_params(), p.astype(np.float32))
+    rng = np.random.default_rng(2)
+    u = rng.normal(size=(3,) + dims).astype(np.float32)
+    f = net.forward(_dev(u), periodic=periodic).cpu().numpy()
+    pad = "wrap" if periodic else "zero"
+    for i in range(3):
+        want, _ = ocnn.forward(p, u[i].astype(np.float64), np.ones(dims), pad)
+        assert np.max(np.abs(f[i] - want)) <= 1e-5 * np.max(np.abs(want))
+
+
+def test_loss_gradient_and_adam_match_oracle():
+    p = _params(3)
+    net = rsd.Cnn(4, 4096)
+    net.set_params(p)
+    rng = np.random.default_rng(4)
+    dims = (12, 11, 13)
+    u = rng.normal(size=(3,) + dims).astype(np.float32)
+    t = rng.normal(size=(3,) + dims).astype(np.float32)
+    sig = np.array([-0.7, -2.0, -5.5])
+    h, margin = 0.25, 2
+    loss, grad, du = net.loss_grad(_dev(u), _dev(t), _dev(sig), h, margin, want_du=True)
+    wl, wg, wdu = ocnn.loss_and_grad(p, u.astype(np.float64), t.astype(np.float64), sig, h, margin)
+    assert loss == pytest.approx(wl, rel=1e-5)
+    for a, b in ((0, 216), (216, 1944), (1944, 2160), (2160, 2162)):
+        assert _rel(grad[a:b], wg[a:b]) <= 1e-4, (a, b)
+    assert _rel(du.cpu().numpy(), wdu) <= 1e-4
+    # Adam from zero moments with the GPU's own gradient
+    net.adam_step(1e-3)
+    want, _, _ = ocnn.adam_step(p, grad.astype(np.float64), np.zeros(ocnn.NP), np.zeros(ocnn.NP), 1, 1e-3)
+    got = net.get_params()
+    assert np.max(np.abs(got - want)) <= 1e-6 * np.max(np.abs(p))
+
+
+@pytest.mark.parametrize("kind,dtype,B", [("sphere", np.float64, 8), ("sphere", np.float32, 16),
+                                          ("periodic", np.float32, 8)])
+def test_precondition_matches_oracle(kind, dtype, B):
+    if kind == "sphere":
+        og = ogrid.build_grid("sphere", 0.3, radius=2.4)
+        g = rsd.Grid("sphere", 0.3, radius=2.4)
+    else:
+        og = ogrid.build_grid("periodic", 0.25, n=16)
+        g = rsd.Grid("periodic", 0.25, n=16)
+    p = _params(5, scale=0.2)
+    N = 2 * B
+    rng = np.random.default_rng(6)
+    r = rng.normal(size=(N, og.np)).astype(dtype)
+    r[3] = 0.0                                   # a zero residual maps to zero
+    sig = -rng.uniform(0.5, 4.0, size=N)
+    net = rsd.Cnn(16, 40000)
+    net.set_params(p)
+    assert net.box(g) == ocnn.box_of(og)[1]
+    out = net.precondition(g, _dev(rsd.to_blocks(r, B)), _dev(sig))
+    got = rsd.from_blocks(out.cpu().numpy()).astype(np.float64)
+    want = ocnn.precondition(p, og, r.astype(np.float64), sig)
+    assert np.all(got[3] == 0.0)
+    assert np.max(np.abs(got - want)) <= 2e-5 * np.max(np.abs(want))
+
+
+def test_crops_match_direct_indexing():
+    og = ogrid.build_grid("sphere", 0.3, radius=2.4)
+    g = rsd.Grid("sphere", 0.3, radius=2.4)
+    _, dims, idx, mask = ocnn.box_of(og)
+    rng = np.random.default_rng(7)
+    B, N = 8, 16
+    r = rng.normal(size=(N, og.np))
+    x = rng.normal(size=(N, og.np))
+    net = rsd.Cnn(4, 40000)
+    desc = np.array([[0, 0, 0, 0], [5, 3, 7, 2], [15, dims[2] - 2, dims[1] - 3, dims[0] - 1]], dtype=np.int32)
+    cd = (4, 5, 6)
+    u, t = net.crops(g, _dev(rsd.to_blocks(r, B)), _dev(rsd.to_blocks(x, B)), desc, cd)
+    u, t = u.cpu().numpy(), t.cpu().numpy()
+    for c, (k, x0, y0, z0) in enumerate(desc):
+        s = np.sqrt(np.mean(r[k] ** 2))
+        rb = np.zeros(int(np.prod(dims)))
+        xb = np.zeros_like(rb)
+        rb[idx], xb[idx] = r[k] / s, x[k] / s
+        rb, xb = rb.reshape(dims), xb.reshape(dims)
+        wu = np.zeros(cd)
+        wt = np.zeros(cd)
+        for zz in range(cd[0]):
+            for yy in range(cd[1]):
+                for xx in range(cd[2]):
+                    Z, Y, X = z0 + zz, y0 + yy, x0 + xx
+                    if Z < dims[0] and Y < dims[1] and X < dims[2]:
+                        wu[zz, yy, xx] = rb[Z, Y, X]
+                        wt[zz, yy, xx] = xb[Z, Y, X]
+        assert np.allclose(u[c], wu, rtol=1e-6, atol=1e-6)
+        assert np.allclose(t[c], wt, rtol=1e-6, atol=1e-6)
+
+
+def test_shifted_solve_periodic_matches_closed_form():
+    og = ogrid.build_grid("periodic", 0.25, n=24)
+    g = rsd.Grid("periodic", 0.25, n=24)
+    rng = np.random.default_rng(8)
+    B, N = 8, 16
+    r = rng.normal(size=(N, og.np))
+    sig = -rng.uniform(0.3, 6.0, size=N)
+    x, it = rsd.shifted_solve(g, _dev(rsd.to_blocks(r, B)), _dev(sig), tol=1e-12, maxit=3000)
+    got = rsd.from_blocks(x.cpu().numpy())
+    want = ocnn.shifted_inverse_periodic(og, r, sig)
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+    assert 0 < it < 3000
+
+
+@pytest.mark.parametrize("dtype,tol,bound", [(np.float64, 1e-10, 1e-9), (np.float32, 1e-5, 1e-4)])
+def test_shifted_solve_sphere_residual(dtype, tol, bound):
+    og = ogrid.build_grid("sphere", 0.3, radius=3.0)
+    g = rsd.Grid("sphere", 0.3, radius=3.0)
+    rng = np.random.default_rng(9)
+    B, N = 8, 8
+    r = rng.normal(size=(N, og.np)).astype(dtype)
+    r[2] = 0.0                                   # zero right-hand side -> zero solution
+    sig = -rng.uniform(0.5, 3.0, size=N)
+    x, it = rsd.shifted_solve(g, _dev(rsd.to_blocks(r, B)), _dev(sig), tol=tol, maxit=2000)
+    got = rsd.from_blocks(x.cpu().numpy()).astype(np.float64)
+    assert np.all(got[2] == 0.0)
+    back = stencil.apply_kinetic(og, got) - sig[:, None] * got
+    r64 = r.astype(np.float64)
+    for k in range(N):
+        if k != 2:
+            assert np.linalg.norm(back[k] - r64[k]) <= bound * np.linalg.norm(r64[k])
+
+
+def test_shifted_solve_reports_nonconvergence():
+    g = rsd.Grid("periodic", 0.25, n=16)
+    r = _dev(rsd.to_blocks(np.random.default_rng(10).normal(size=(8, g.np)), 8))
+    with pytest.raises(rsd.RsError) as e:
+        rsd.shifted_solve(g, r, _dev(np.full(8, -1.0)), tol=1e-14, maxit=3)
+    assert e.value.code == rsd._abi.RS_ENOTCONV
+
+
+def test_bad_arguments_raise():
+    with pytest.raises(rsd.RsError):
+        rsd.Cnn(0, 100)
+    net = rsd.Cnn(2, 100)
+    with pytest.raises(rsd.RsError):
+        net.forward(_dev(np.zeros((3, 4, 4, 4), np.float32)))    # batch above max_batch
+    g = rsd.Grid("periodic", 0.25, n=16)                          # box 4096 > max_box
+    with pytest.raises(rsd.RsError):
+        net.precondition(g, _dev(np.zeros((1, g.np, 2), np.float32)), _dev(-np.ones(2)))
