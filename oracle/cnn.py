@@ -23,11 +23,16 @@ Preconditioner for a residual r of a state with shift sigma < 0:
     s    = rms of r over the domain points,
     K(r) = s * g(sigma) * f(r / s),   g = softplus(a + b log(-sigma h^2)),
 so K(-r) = -K(r) and K(c r) = c K(r) for c > 0.  Training pairs are
-(r, x = (T - sigma)^-1 r) with sigma = -<psi|T|psi>; the loss of a batch is
-sum_i |g_i f(u_i) - t_i|^2 / sum_i |t_i|^2 over the points at least `margin`
-away from the crop faces (u = r/s, t = x/s).  The ratio is taken over the
-whole batch: per-crop ratios are unbounded on crops where a localised state's
-target nearly vanishes.
+(r, x = (T - sigma)^-1 r) with sigma = -<psi|T|psi>.  The loss of a batch
+measures the error in the energy norm of A_i = T - sigma_i (the norm in which
+a preconditioner is judged: an error at wave number k weighs k^2/2 - sigma,
+so wrong short-wavelength output, which the plain L2 norm of the smooth
+target barely sees, is penalised):
+    L = sum_i <e_i|A_i|e_i> / sum_i <t_i|A_i|t_i>,  e_i = M (g_i f(u_i) - t_i),
+t_i masked by M too, M the points at least `margin` from the crop faces
+(u = r/s, t = x/s), A_i applied on the crop with zero outside it.  The ratio
+is over the whole batch: per-crop ratios are unbounded on crops where a
+localised state's target nearly vanishes.
 
 Parameters are one flat vector: w1 (216), w2 (1728), w3 (216), a, b.
 """
@@ -35,7 +40,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .stencil import kinetic_symbol
+from .stencil import fd_weights, kinetic_symbol
 
 SHAPES = ((8, 1, 3, 3, 3), (8, 8, 3, 3, 3), (1, 8, 3, 3, 3))
 NW = sum(int(np.prod(s)) for s in SHAPES)      # 2160
@@ -135,6 +140,17 @@ def gain(params: np.ndarray, sigma, h: float):
     return softplus(a + b * np.log(-np.asarray(sigma) * h * h))
 
 
+def box_kinetic(x: np.ndarray, h: float) -> np.ndarray:
+    """T x on a dense box [Z, Y, X] with zero outside: the 25-point star of
+    Sec. 5.1, -1/(2h^2) sum_axes sum_m c_m (x_{p+m} + x_{p-m} - 2 x_p)."""
+    c = fd_weights(4)
+    out = np.zeros_like(x)
+    for m in range(1, 5):
+        for d in ((m, 0, 0), (0, m, 0), (0, 0, m)):
+            out += c[m] * (shift(x, *d, "zero") + shift(x, *(-v for v in d), "zero") - 2.0 * x)
+    return -0.5 / (h * h) * out
+
+
 def loss_and_grad(params: np.ndarray, u: np.ndarray, t: np.ndarray, sigma: np.ndarray,
                   h: float, margin: int, pad: str = "zero"):
     """Batch u, t [n, Z, Y, X], sigma [n]; crops are whole boxes (mask 1).
@@ -145,7 +161,11 @@ def loss_and_grad(params: np.ndarray, u: np.ndarray, t: np.ndarray, sigma: np.nd
     Z, Y, X = u.shape[1:]
     inner[margin:Z - margin, margin:Y - margin, margin:X - margin] = 1.0
     mask = np.ones(u.shape[1:])
-    tt = sum(np.sum(inner * t[i] ** 2) for i in range(n))
+
+    def A(i, x):
+        return box_kinetic(x, h) - sigma[i] * x
+
+    den = sum(np.sum((inner * t[i]) * A(i, inner * t[i])) for i in range(n))
     grad = np.zeros(NP)
     du = np.zeros_like(u)
     loss = 0.0
@@ -155,8 +175,9 @@ def loss_and_grad(params: np.ndarray, u: np.ndarray, t: np.ndarray, sigma: np.nd
         z = a + b * ell
         g = softplus(z)
         e = inner * (g * f - t[i])
-        loss += np.sum(e ** 2) / tt
-        dpred = 2.0 * e / tt
+        Ae = A(i, e)
+        loss += np.sum(e * Ae) / den
+        dpred = 2.0 * inner * Ae / den
         dw, du[i] = backward(params, cache, g * dpred, mask, pad)
         grad[:NW] += dw
         dg = np.sum(dpred * f)

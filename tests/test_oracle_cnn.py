@@ -89,7 +89,41 @@ def test_loss_zero_at_exact_fit():
     p0[1944:2160] = 0.0
     t = rng.normal(size=(2, 6, 6, 6))
     loss, _, _ = cnn.loss_and_grad(p0, rng.normal(size=(2, 6, 6, 6)), t, np.array([-2.0, -1.0]), 0.25, 1)
-    assert loss == pytest.approx(1.0, rel=1e-14)
+    assert loss == pytest.approx(1.0, rel=1e-13)
+
+
+def test_box_kinetic_matches_grid_stencil():
+    """The dense-box kinetic operator of the loss equals the oracle's grid
+    stencil on a Dirichlet box of the same size (points mapped by their
+    integer coordinates)."""
+    g = grid.build_grid("box", 0.25, n=9)
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=g.np)
+    want = stencil.apply_kinetic(g, x)
+    box = np.zeros((9, 9, 9))
+    u = g.inner - g.inner.min(axis=0)
+    box[u[:, 2], u[:, 1], u[:, 0]] = x
+    got = cnn.box_kinetic(box, 0.25)[u[:, 2], u[:, 1], u[:, 0]]
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.max(np.abs(want)))
+
+
+def test_energy_norm_loss_weights_short_waves():
+    """For a zero network the loss is one; an error made of a short wave
+    costs more than the same L2 error made of a long wave."""
+    rng = np.random.default_rng(12)
+    p = _params(rng)
+    p0 = p.copy()
+    p0[1944:2160] = 0.0
+    t = rng.normal(size=(1, 12, 12, 12))
+    loss, _, _ = cnn.loss_and_grad(p0, rng.normal(size=(1, 12, 12, 12)), t, np.array([-1.0]), 0.25, 2)
+    assert loss == pytest.approx(1.0, rel=1e-13)
+    zz = np.arange(12)[:, None, None] * np.ones((1, 12, 12))
+    slow = np.cos(2 * np.pi * zz / 12.0)
+    fast = np.cos(np.pi * zz)
+    e_slow = cnn.box_kinetic(slow, 0.25) + 1.0 * slow
+    e_fast = cnn.box_kinetic(fast, 0.25) + 1.0 * fast
+    inner = (slice(4, 8),) * 3
+    assert np.sum(fast[inner] * e_fast[inner]) > 10 * np.sum(slow[inner] * e_slow[inner])
 
 
 def test_adam_first_steps_closed_form():
