@@ -140,6 +140,69 @@ def cpu_baseline(w, budget_s=15.0):
                        f"states on the {og.np}-point grid, {el:.1f} s")
 
 
+def traffic_probe(w, dtype, B):
+    """Kernels for the FETCH_SIZE / WRITE_SIZE passes: an elementwise kernel
+    that reads 1 GiB and writes 1 GiB (its counters calibrate bytes per
+    counted KiB), then the stencil."""
+    import torch
+    import paper_1306_2953_amd as rsd
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    S = setup(w, dtype, B)
+    for _ in range(3):
+        rsd.hpsi_block(S["g"], S["nl"], S["v"], S["psi"], S["hpsi"])
+    torch.cuda.synchronize()
+    log(f"traffic probe done: 1 GiB read + 1 GiB write x3, H psi x3 ({w.name}, {dtype}, B {B})")
+
+
+def _counter_means(path, counter):
+    import csv
+    import collections
+    per = collections.defaultdict(list)
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] == counter:
+                per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def traffic_record(w, dtype, fetch_csv, write_csv):
+    """Calibrated HBM bytes per H psi call of the stencil kernel (interior
+    and surface launches): counted KiB x (1 GiB / the KiB the counter shows
+    for the 1 GiB calibration kernel)."""
+    out = {}
+    for key, path, counter in (("read", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        m = _counter_means(path, counter)
+        cal = [v for k, v in m.items() if "elementwise_kernel" in k and "Fill" not in k]
+        if not cal:
+            raise SystemExit(f"no calibration kernel in {path}")
+        factor = float(1 << 30) / (cal[0] * 1024.0)
+        kib = sum(v for k, v in m.items() if "hpsi_brick_kernel" in k)
+        out[key] = dict(counted_kib=kib, calibration_kib_per_gib=cal[0], bytes=kib * 1024.0 * factor)
+    path = os.path.join(ROOT, "profiles", "hpsi_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    rec[f"{w.name}/{dtype}"] = {
+        "bytes_per_launch": out["read"]["bytes"] + out["write"]["bytes"],
+        "read_bytes": out["read"]["bytes"], "write_bytes": out["write"]["bytes"],
+        "fetch_counted_kib": out["read"]["counted_kib"], "write_counted_kib": out["write"]["counted_kib"],
+        "fetch_kib_per_gib_read": out["read"]["calibration_kib_per_gib"],
+        "write_kib_per_gib_written": out["write"]["calibration_kib_per_gib"],
+        "source_sha256_16": stencil_source_hash(),
+    }
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    log(f"traffic: {rec[f'{w.name}/{dtype}']}")
+
+
 def stencil_source_hash() -> str:
     with open(os.path.join(ROOT, "paper_1306_2953_amd", "csrc", "hpsi.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -239,12 +302,33 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
+    ap.add_argument("--profile-eig", type=int, default=0, metavar="K",
+                    help="for kernel-trace runs: K eigensolver steps of the FP64 sphere and of "
+                         "its FP32 split-precision form from the seeded start; prints step times")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter_collection.csv files of the FETCH_SIZE and WRITE_SIZE "
+                         "passes over --traffic-probe into profiles/hpsi_traffic.json")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for counter runs: three 1 GiB device copies (calibration), then "
+                         "three H psi applications of the workload; prints nothing")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     w = synthetic.CONFIGS[a.config]
     B = a.block or w.block
+    if a.profile_eig:
+        for cfg, dt in ((2, "f64"), (3, "f32")):
+            r = eigensolve_run(synthetic.CONFIGS[cfg], dt, synthetic.CONFIGS[cfg].block, a.profile_eig, 0.0,
+                               log_every=1)
+            log(f"{synthetic.CONFIGS[cfg].name} {dt}: step times {np.diff([0.0] + r['times'])}")
+        return
+    if a.traffic_record:
+        traffic_record(w, "f32" if a.config in (3, 4, 5) else "f64", *a.traffic_record)
+        return
+    if a.traffic_probe:
+        traffic_probe(w, "f32" if a.config in (3, 4, 5) else "f64", B)
+        return
     dtype = "f32" if a.config in (3, 4, 5) else "f64"
     log(f"workload {w.name} dtype {dtype} B {B}")
     r = run_gpu(w, dtype, B, a.steps, a.warmup)

@@ -316,8 +316,11 @@ rs_status rs_cnn_forward(rs_cnn *c, const float *u, float *f, int32_t n,
 
 /* Training loss and gradient on a batch of crops u (network input r/s),
  * t (target x/s), shifts sigma (DEVICE double [n], < 0), zero outside each
- * crop: loss = sum_i |g_i f(u_i) - t_i|^2 / sum_i |t_i|^2 over the points
- * at least `margin` from the crop faces.  The gradient (all RS_CNN_NPARAM
+ * crop.  The error is measured in the energy norm of A_i = T - sigma_i
+ * (T the 25-point stencil on the crop, zero outside):
+ * loss = sum_i <e_i|A_i e_i> / sum_i <M t_i|A_i M t_i>,
+ * e_i = M (g_i f(u_i) - t_i), M the points at least `margin` from the crop
+ * faces.  The gradient (all RS_CNN_NPARAM
  * values, FP32 with FP64 sums over points) is kept for rs_cnn_adam_step and
  * copied to grad (HOST, may be NULL); du (DEVICE [n][Z][Y][X], may be NULL)
  * receives dloss/du.  Synchronises when loss or grad is given. */

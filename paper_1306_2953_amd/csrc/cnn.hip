@@ -198,26 +198,62 @@ __global__ void gain_kernel(const float *__restrict__ params, const double *__re
     gz[3 * i + 2] = l;
 }
 
-// Per (chunk, sample) sums over the points at least `margin` from the box
-// faces: e^2, t^2, e f with e = g f - t.
+__device__ __forceinline__ bool interior(int q, int Z, int Y, int X, int margin) {
+    const int x = q % X, y = (q / X) % Y, z = q / (X * Y);
+    return !(x < margin || y < margin || z < margin || x >= X - margin || y >= Y - margin || z >= Z - margin);
+}
+
+// em = M (g f - t), tm = M t (M: points at least `margin` from the faces).
+__global__ void err_kernel(const float *__restrict__ f, const float *__restrict__ t, const double *__restrict__ gz,
+                           int Z, int Y, int X, int margin, int n, float *__restrict__ em, float *__restrict__ tm) {
+    const int vol = Z * Y * X;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    if (gid >= vol * n) return;
+    const int i = gid / vol, q = gid - i * vol;
+    const bool in = interior(q, Z, Y, X, margin);
+    em[gid] = in ? (float)(gz[3 * i] * (double)f[gid] - (double)t[gid]) : 0.f;
+    tm[gid] = in ? t[gid] : 0.f;
+}
+
+// out = (T - sigma_i) x on each box, zero outside: the 25-point star of
+// Sec. 5.1 in first-difference form.
+__global__ void kin_kernel(const float *__restrict__ x, float *__restrict__ out, const double *__restrict__ sigma,
+                           double h, int Z, int Y, int X, int n) {
+    const int vol = Z * Y * X;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    if (gid >= vol * n) return;
+    const int i = gid / vol, q = gid - i * vol;
+    const int cx = q % X, cy = (q / X) % Y, cz = q / (X * Y);
+    const float *b = x + (int64_t)i * vol;
+    const float c[5] = {0.f, 8.f / 5.f, -1.f / 5.f, 8.f / 315.f, -1.f / 560.f};
+    const float v = b[q];
+    float acc = 0.f;
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+        const float xm = cx - m >= 0 ? b[q - m] : 0.f, xp = cx + m < X ? b[q + m] : 0.f;
+        const float ym = cy - m >= 0 ? b[q - m * X] : 0.f, yp = cy + m < Y ? b[q + m * X] : 0.f;
+        const float zm = cz - m >= 0 ? b[q - m * X * Y] : 0.f, zp = cz + m < Z ? b[q + m * X * Y] : 0.f;
+        acc += c[m] * (((xm - v) + (xp - v)) + ((ym - v) + (yp - v)) + ((zm - v) + (zp - v)));
+    }
+    out[gid] = (float)(-0.5 / (h * h) * (double)acc - sigma[i] * (double)v);
+}
+
+// Per (chunk, sample) sums: <em|A em>, <tm|A tm>, <M f|A em>.
 __global__ void __launch_bounds__(256)
-loss_partial_kernel(const float *__restrict__ f, const float *__restrict__ t, const double *__restrict__ gz, int Z,
-                    int Y, int X, int margin, int nch, double *__restrict__ partial) {
+loss_partial_kernel(const float *__restrict__ em, const float *__restrict__ ae, const float *__restrict__ tm,
+                    const float *__restrict__ at, const float *__restrict__ f, int Z, int Y, int X, int margin,
+                    int nch, double *__restrict__ partial) {
     __shared__ double red[3][256];
     const int i = blockIdx.y, tid = threadIdx.x;
     const int vol = Z * Y * X, per = (vol + nch - 1) / nch;
     const int q0 = blockIdx.x * per, q1 = min(vol, q0 + per);
-    const double g = gz[3 * i];
     double a0 = 0, a1 = 0, a2 = 0;
     for (int q = q0 + tid; q < q1; q += 256) {
-        const int x = q % X, y = (q / X) % Y, z = q / (X * Y);
-        if (x < margin || y < margin || z < margin || x >= X - margin || y >= Y - margin || z >= Z - margin)
-            continue;
-        const double fv = f[(int64_t)i * vol + q], tv = t[(int64_t)i * vol + q];
-        const double e = g * fv - tv;
-        a0 += e * e;
-        a1 += tv * tv;
-        a2 += e * fv;
+        const int64_t k = (int64_t)i * vol + q;
+        const double aev = ae[k];
+        a0 += (double)em[k] * aev;
+        a1 += (double)tm[k] * (double)at[k];
+        if (interior(q, Z, Y, X, margin)) a2 += (double)f[k] * aev;
     }
     red[0][tid] = a0;
     red[1][tid] = a1;
@@ -231,8 +267,8 @@ loss_partial_kernel(const float *__restrict__ f, const float *__restrict__ t, co
     if (tid < 3) partial[((int64_t)i * nch + blockIdx.x) * 3 + tid] = red[tid][0];
 }
 
-// loss = sum_i e2_i / sum_i t2_i; coef_i = 2 / sum_i t2_i (so dL/dpred =
-// coef e); gradient of the gain parameters into grad[kNW], grad[kNW + 1].
+// loss = sum_i <e|Ae>_i / sum_i <t|At>_i; coef = 2 / sum_i <t|At>_i (so
+// dL/dpred = coef M A e); gain-parameter gradient into grad[kNW], grad[kNW + 1].
 __global__ void loss_final_kernel(const double *__restrict__ partial, int n, int nch, const double *__restrict__ gz,
                                   double *__restrict__ coef, double *__restrict__ loss, float *__restrict__ grad) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -258,18 +294,14 @@ __global__ void loss_final_kernel(const double *__restrict__ partial, int n, int
     grad[kNW + 1] = (float)gb;
 }
 
-__global__ void df_kernel(const float *__restrict__ f, const float *__restrict__ t, const double *__restrict__ gz,
+__global__ void df_kernel(const float *__restrict__ ae, const double *__restrict__ gz,
                           const double *__restrict__ coef, int Z, int Y, int X, int margin, int n,
                           float *__restrict__ df) {
     const int vol = Z * Y * X;
     const int gid = blockIdx.x * 256 + threadIdx.x;
     if (gid >= vol * n) return;
     const int i = gid / vol, q = gid - i * vol;
-    const int x = q % X, y = (q / X) % Y, z = q / (X * Y);
-    const bool in = !(x < margin || y < margin || z < margin || x >= X - margin || y >= Y - margin ||
-                      z >= Z - margin);
-    const double g = gz[3 * i];
-    df[gid] = in ? (float)(g * coef[i] * (g * (double)f[gid] - (double)t[gid])) : 0.f;
+    df[gid] = interior(q, Z, Y, X, margin) ? (float)(gz[3 * i] * coef[i] * (double)ae[gid]) : 0.f;
 }
 
 // Adam (Kingma and Ba, 2015): c1 = 1 - beta1^t, c2 = 1 - beta2^t.
@@ -627,12 +659,17 @@ extern "C" rs_status rs_cnn_loss_grad(rs_cnn *c, const float *u, const float *t,
     float *a1 = c->a1.as<float>(), *a2 = c->a2.as<float>(), *d1 = c->d1.as<float>(), *d2 = c->d2.as<float>();
     if ((s = forward(c, u, f, n, Z, Y, X, 0, nullptr, st))) return s;
     hipLaunchKernelGGL(gain_kernel, dim3((n + 255) / 256), dim3(256), 0, st, P, sigma, h, n, c->gz.as<double>());
-    hipLaunchKernelGGL(loss_partial_kernel, dim3(nch, n), dim3(256), 0, st, f, t, c->gz.as<double>(), Z, Y, X,
-                       margin, nch, c->lpart.as<double>());
+    // energy-norm error terms in the (not yet used) delta buffer d1
+    float *em = d1, *tm = d1 + tot, *ae = d1 + 2 * tot, *at = d1 + 3 * tot;
+    hipLaunchKernelGGL(err_kernel, dim3(gsz), dim3(256), 0, st, f, t, c->gz.as<double>(), Z, Y, X, margin, n, em, tm);
+    hipLaunchKernelGGL(kin_kernel, dim3(gsz), dim3(256), 0, st, em, ae, sigma, h, Z, Y, X, n);
+    hipLaunchKernelGGL(kin_kernel, dim3(gsz), dim3(256), 0, st, tm, at, sigma, h, Z, Y, X, n);
+    hipLaunchKernelGGL(loss_partial_kernel, dim3(nch, n), dim3(256), 0, st, em, ae, tm, at, f, Z, Y, X, margin, nch,
+                       c->lpart.as<double>());
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, st, c->lpart.as<double>(), n, nch,
                        c->gz.as<double>(), c->coef.as<double>(), c->loss.as<double>(), G);
-    hipLaunchKernelGGL(df_kernel, dim3(gsz), dim3(256), 0, st, f, t, c->gz.as<double>(), c->coef.as<double>(), Z, Y,
-                       X, margin, n, df);
+    hipLaunchKernelGGL(df_kernel, dim3(gsz), dim3(256), 0, st, ae, c->gz.as<double>(), c->coef.as<double>(), Z, Y, X,
+                       margin, n, df);
     hipLaunchKernelGGL(flip_kernel, dim3((kNW + 255) / 256), dim3(256), 0, st, P, WT);
     RS_HIP(hipGetLastError());
     // layer 3: weights, then delta of layer 2 (through tanh)

@@ -41,13 +41,18 @@ template <> __device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t off
 template <> __device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
+// Cache policy of the field stores: non-temporal (the outputs are not read
+// again by this kernel, so they should not evict neighbour data from L2).
+#ifndef RS_STORE_AUX
+#define RS_STORE_AUX 2
+#endif
 template <typename T> __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t off);
 template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, RS_STORE_AUX);
 }
 template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, uint32_t off) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, RS_STORE_AUX);
 }
 
 // Byte offset of the point in slot q of a brick (mask, start), scaled by
@@ -123,11 +128,13 @@ struct Slots {
         if constexpr (FAST) {
             if constexpr (sizeof(T) == 4)
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r,
-                                                      (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW), 0);
+                                                      (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW),
+                                                      RS_STORE_AUX);
             else {
                 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
                 __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r,
-                                                      (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW), 0);
+                                                      (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW),
+                                                      RS_STORE_AUX);
             }
         } else {
             bstore<T>(v, r, __builtin_elementwise_add_sat(lane_off, tbl[q]));
@@ -158,7 +165,7 @@ __device__ __forceinline__ void phase_fence(T (&acc)[N]) {
 }
 #define RS_PHASE() phase_fence(acc)
 #ifndef RS_PHASE_LINES
-#define RS_PHASE_LINES 2     // stencil lines per phase
+#define RS_PHASE_LINES 4     // stencil lines per phase
 #endif
 
 // One wave computes NZ z-planes (from plane Z0) of one brick for 64 state
