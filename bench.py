@@ -265,6 +265,90 @@ def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every
                 ms_per_step=step_ms, keep=keep)
 
 
+def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
+    """FP32 solve of the periodic workload with the trained network against
+    the same solve with the filter, from the same seeded start.  The network
+    is trained first on the GPU (30 recorded filter steps, CG targets,
+    energy-norm loss).  Reference eigenvalues: the end of whichever run
+    reaches the smaller residual on the lowest N - nbuf states."""
+    import torch
+    import paper_1306_2953_amd as rsd
+    from paper_1306_2953_amd import learned
+    g = rsd.Grid.for_workload(w)
+    atoms = synthetic.draw_atoms(w)
+    v = synthetic.potential_for(w, g.xyz(), atoms)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=w.nstates)
+    tv = torch.from_numpy(v.astype(np.float32)).cuda()
+    psi0 = torch.from_numpy(rsd.to_blocks(
+        synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np).astype(np.float32), w.block)).cuda()
+    rsd.Context(g, w.nstates).orthonormalize(psi0)
+    keep = w.nstates - nbuf
+    box = int(np.prod([g.nb[a] * 4 for a in range(3)]))
+    net = rsd.Cnn(max(32, w.block), max(box, 16 ** 3))
+    net.set_params(learned.init_params(0))
+    rng = np.random.default_rng(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = rsd.Eigensolver(g, nl, tv, w.nstates, w.block, tol=1e-5, record=True)
+    pairs = learned.collect_pairs(g, rec, psi0.clone(), net, steps=30, crops_per_state=2, crop=16, rng=rng,
+                                  cg_tol=1e-5)
+    del rec
+    t_collect = time.perf_counter() - t0
+    val = pairs.subset(pairs.state % 10 == 9)
+    tr = pairs.subset(pairs.state % 10 != 9)
+    t0 = time.perf_counter()
+    learned.train(net, tr, g.h, iters=train_iters, batch=32, lr=learned.cosine_lr(3e-3, 1e-5, train_iters),
+                  margin=3, rng=rng)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    vloss = learned.evaluate(net, val, g.h, 3, 32)
+    npairs = pairs.n
+    del pairs, tr, val
+    torch.cuda.empty_cache()
+    runs = {}
+    for name, pre in (("filter", None), ("learned", net)):
+        s = rsd.Eigensolver(g, nl, tv, w.nstates, w.block, tol=1e-6)
+        if pre is not None:
+            s.set_precond(pre)
+        x = psi0.clone()
+        el, times, eigs, maxres = 0.0, [], [], []
+        for k in range(max_steps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            eig, res, _ = s.step(x)
+            el += time.perf_counter() - t1
+            times.append(el)
+            eigs.append(eig.copy())
+            maxres.append(float(res[:keep].max()))
+            last_res = res[:keep].copy()
+            if k % 20 == 0:
+                log(f"  learned compare {name} step {k}: max res {maxres[-1]:.2e} t {el:.2f} s")
+            if maxres[-1] < 1e-5:
+                break
+        runs[name] = dict(times=times, eigs=eigs, maxres=maxres, last_res=last_res)
+        del s, x
+        torch.cuda.empty_cache()
+    best = min(runs, key=lambda n: runs[n]["maxres"][-1])
+    ref_res = runs[best]["maxres"][-1]
+    ref = runs[best]["eigs"][-1] if ref_res < 1e-5 else None   # eigenvalue error ~ residual^2
+    out = {"workload": w.name, "states": w.nstates, "measured_states": keep,
+           "reference": (f"final eigenvalues of the {best} run (max residual {ref_res:.1e})" if ref is not None
+                         else f"none: neither run reached residual 1e-5 (best {best}, {ref_res:.1e})"),
+           "training": {"pairs": npairs, "iterations": train_iters, "collect_s": t_collect,
+                        "train_s": t_train, "validation_energy_norm_loss": vloss}}
+    for name, r in runs.items():
+        hit = None
+        if ref is not None:
+            hit = next((k for k, e in enumerate(r["eigs"]) if np.max(np.abs(e[:keep] - ref[:keep])) < 1e-6), None)
+        out[name] = {"steps_run": len(r["times"]), "final_max_residual": r["maxres"][-1],
+                     "final_median_residual": float(np.median(r["last_res"])),
+                     "lowest_eigenvalue": float(r["eigs"][-1][0]),
+                     "ms_per_step": 1e3 * r["times"][-1] / len(r["times"]),
+                     "time_to_1e-6_s": None if hit is None else r["times"][hit],
+                     "steps_to_1e-6": None if hit is None else hit + 1}
+    return out
+
+
 def eigensolve_compare(max_steps=600):
     """Plain FP64 filter solve on the 128-state sphere (its converged end is
     the reference) against the FP32 split-precision solve of the same system."""
@@ -302,6 +386,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--profile-eig", type=int, default=0, metavar="K",
                     help="for kernel-trace runs: K eigensolver steps of the FP64 sphere and of "
                          "its FP32 split-precision form from the seeded start; prints step times")
@@ -344,6 +429,11 @@ def main():
     if a.config == 2 and not a.no_eig:
         eig = eigensolve_compare()
         log(f"eigensolve: {eig}")
+    lrn = None
+    if a.config == 2 and not a.no_learned:
+        log("learned preconditioner: periodic workload")
+        lrn = learned_compare(synthetic.CONFIGS[4])
+        log(f"learned: {lrn}")
     cpu = None
     if not a.no_cpu:
         log("cpu baseline")
@@ -368,6 +458,7 @@ def main():
                      "bytes_per_launch": r["bytes_kernel"],
                      "avg_launch_s": r["t_kernel"]},
         "eigensolve": eig,
+        "learned_preconditioner": lrn,
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -260,9 +260,13 @@ typedef struct {
                             rs_eigensolve_residuals (training data)          */
 } rs_solver_opts;
 
-/* nstates (a multiple of B, <= 256) states of dtype on grid g with local
- * potential vloc (DEVICE [np] of dtype; must stay valid for the solver's
- * lifetime) and optional projectors nl.  opts NULL: m = 3, alpha = 1/2,
+/* nstates (<= 256) states of dtype in nblk = ceil(nstates / B) blocks on
+ * grid g with local potential vloc (DEVICE [np] of dtype; must stay valid
+ * for the solver's lifetime) and optional projectors nl (max_states >=
+ * nblk * B).  When B does not divide nstates the last block is padded with
+ * zero states: they stay zero, get identity pivots in the orthonormalisation
+ * and are left out of the Rayleigh-Ritz problem, the stopping rule and the
+ * outputs.  opts NULL: m = 3, alpha = 1/2,
  * tol = 1e-6, block_stop = 1, record = 0.  Allocates all workspaces (about 2(m+1)+3
  * field arrays of np * nstates elements). */
 rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc,
@@ -270,8 +274,8 @@ rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vl
                                const rs_solver_opts *opts, rs_solver **out);
 void rs_eigensolve_destroy(rs_solver *s);
 
-/* One step on psi (DEVICE [nstates/B][np][B], orthonormal on entry; updated
- * in place).  eig and resnorm (HOST double [nstates], may be NULL) receive
+/* One step on psi (DEVICE [nblk][np][B], the first nstates states
+ * orthonormal and the padding states zero on entry; updated in place).  eig and resnorm (HOST double [nstates], may be NULL) receive
  * the step's Rayleigh-Ritz eigenvalues and residual norms; *nconv (HOST, may
  * be NULL) the number of states with resnorm < tol.  Synchronises the stream
  * once.  Errors: RS_ENOTPOSDEF if the final orthonormalisation fails,
@@ -369,7 +373,7 @@ rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c);
 
 /* With opts.record: the last step's residuals R0 (after Rayleigh-Ritz) and
  * shifts sigma_k = -<psi_k|T|psi_k> into R (DEVICE, the psi layout) and
- * sigma (DEVICE double [nstates]).  Asynchronous. */
+ * sigma (DEVICE double [nblk * B]; 0 for padding states).  Asynchronous. */
 rs_status rs_eigensolve_residuals(rs_solver *s, void *R, double *sigma, void *stream);
 
 #ifdef __cplusplus

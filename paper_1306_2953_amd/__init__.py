@@ -282,6 +282,7 @@ class Eigensolver:
                  record: bool = False):
         self.grid, self.nl, self.vloc = grid, nl, vloc     # vloc kept alive here
         self.nstates, self.B = nstates, B
+        self.nblk = -(-nstates // B)          # the last block may be zero-padded
         self.dtype = vloc.dtype
         self.precond = None
         o = _abi.SolverOpts()
@@ -295,8 +296,8 @@ class Eigensolver:
     def step(self, psi, stream=None):
         """One step in place; returns (eig, resnorm, nconv) on the host."""
         nblk, B = _blocks(psi, self.grid)
-        if nblk * B != self.nstates or B != self.B:
-            raise ValueError("psi does not match the solver's states")
+        if nblk != self.nblk or B != self.B:
+            raise ValueError("psi does not match the solver's blocks")
         eig = np.empty(self.nstates)
         res = np.empty(self.nstates)
         nconv = ctypes.c_int32(0)
@@ -313,8 +314,8 @@ class Eigensolver:
     def residuals(self, stream=None):
         """(R0 [nblk, np, B], sigma [N]) of the last step (needs record=True)."""
         torch = _torch()
-        R = torch.empty((self.nstates // self.B, self.grid.np, self.B), dtype=self.dtype, device="cuda")
-        sig = torch.empty(self.nstates, dtype=torch.float64, device="cuda")
+        R = torch.empty((self.nblk, self.grid.np, self.B), dtype=self.dtype, device="cuda")
+        sig = torch.empty(self.nblk * self.B, dtype=torch.float64, device="cuda")
         check(lib().rs_eigensolve_residuals(self._h, _dev(R, "R"), _dev(sig, "sigma"), _stream(stream)))
         return R, sig
 
@@ -436,14 +437,18 @@ def shifted_solve(grid: Grid, r, sigma, tol: float = 1e-8, maxit: int = 2000, st
 
 
 def to_blocks(states: np.ndarray, B: int) -> np.ndarray:
-    """State-major [N, np] -> block layout [N/B, np, B] (host-side reshuffle)."""
+    """State-major [N, np] -> block layout [ceil(N/B), np, B] (host-side
+    reshuffle); a partial last block is padded with zero states."""
     N, npts = states.shape
-    if N % B:
-        raise ValueError("N must be a multiple of B")
-    return np.ascontiguousarray(states.reshape(N // B, B, npts).transpose(0, 2, 1))
+    nblk = -(-N // B)
+    if nblk * B != N:
+        states = np.concatenate([states, np.zeros((nblk * B - N, npts), dtype=states.dtype)])
+    return np.ascontiguousarray(states.reshape(nblk, B, npts).transpose(0, 2, 1))
 
 
-def from_blocks(blocks: np.ndarray) -> np.ndarray:
-    """Block layout [nblk, np, B] -> state-major [nblk*B, np]."""
+def from_blocks(blocks: np.ndarray, n: Optional[int] = None) -> np.ndarray:
+    """Block layout [nblk, np, B] -> state-major [n, np] (default all
+    nblk*B states; n drops the padding)."""
     nblk, npts, B = blocks.shape
-    return np.ascontiguousarray(blocks.transpose(0, 2, 1).reshape(nblk * B, npts))
+    out = np.ascontiguousarray(blocks.transpose(0, 2, 1).reshape(nblk * B, npts))
+    return out if n is None else out[:n]

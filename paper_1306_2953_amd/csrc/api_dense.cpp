@@ -85,16 +85,18 @@ extern "C" rs_status rs_eigh(rs_ctx *c, double *A, double *V, double *evals, int
     return rs::eigh(c->w, A, V, evals, N, (hipStream_t)stream);
 }
 
-extern "C" rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk, int32_t B, int32_t dtype,
-                                             int32_t prec, double *S_out, int32_t *info, void *stream) {
+// nreal < nblk * B: the states from nreal on are zero padding (they get an
+// identity pivot and stay zero).
+rs_status orthonormalize_impl(rs_ctx *c, void *psi, int nblk, int B, int dtype, int prec, double *S_out,
+                              int32_t *info, int nreal, hipStream_t s) {
     rs_status st = check(c, nblk, B, dtype, prec, "rs_orthonormalize_block");
     if (st) return st;
     if (!psi) return rs::fail(RS_EINVAL, "rs_orthonormalize_block: null psi");
-    hipStream_t s = (hipStream_t)stream;
     const int N = nblk * B;
     const double dv = c->g->h * c->g->h * c->g->h;
     double *S = S_out ? S_out : c->S.as<double>();
     if ((st = rs::gram(c->w, psi, psi, c->g->np, B, nblk, dtype, prec, dv, S, 0, s))) return st;
+    if ((st = rs::pad_identity(S, N, nreal, s))) return st;
     if ((st = rs::cholesky(c->w, S, c->U.as<double>(), N, c->info.as<int>(), s))) return st;
     if ((st = rs::trinv(c->U.as<double>(), c->T.as<double>(), N, c->info.as<int>(), s))) return st;
     if ((st = rs::rotate(c->w, psi, c->T.as<double>(), c->g->np, B, nblk, dtype, prec, c->info.as<int>(), s)))
@@ -108,21 +110,28 @@ extern "C" rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk,
     return RS_OK;
 }
 
+extern "C" rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk, int32_t B, int32_t dtype,
+                                             int32_t prec, double *S_out, int32_t *info, void *stream) {
+    return orthonormalize_impl(c, psi, nblk, B, dtype, prec, S_out, info, nblk * B, (hipStream_t)stream);
+}
+
 rs_status subspace_diag_capped(rs_ctx *c, void *psi, void *hpsi, double *eig, int nblk, int B, int dtype,
-                               int prec, int max_sweeps, hipStream_t s) {
+                               int prec, int max_sweeps, int nreal, hipStream_t s) {
     rs_status st = check(c, nblk, B, dtype, prec, "rs_subspace_diag");
     if (st) return st;
     if (!psi || !hpsi || !eig) return rs::fail(RS_EINVAL, "rs_subspace_diag: null pointer");
     const int N = nblk * B;
     const double dv = c->g->h * c->g->h * c->g->h;
     if ((st = rs::gram(c->w, psi, hpsi, c->g->np, B, nblk, dtype, prec, dv, c->A.as<double>(), 2, s))) return st;
-    if ((st = rs::eigh(c->w, c->A.as<double>(), c->V.as<double>(), eig, N, s, max_sweeps))) return st;
+    if ((st = rs::eigh_leading(c->w, c->A.as<double>(), c->V.as<double>(), eig, N, nreal, c->S.as<double>(),
+                               c->U.as<double>(), s, max_sweeps)))
+        return st;
     if ((st = rs::rotate(c->w, psi, c->V.as<double>(), c->g->np, B, nblk, dtype, prec, nullptr, s))) return st;
     return rs::rotate(c->w, hpsi, c->V.as<double>(), c->g->np, B, nblk, dtype, prec, nullptr, s);
 }
 
 extern "C" rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_t nblk, int32_t B,
                                       int32_t dtype, int32_t prec, void *stream) {
-    return subspace_diag_capped(c, psi, hpsi, eig, nblk, B, dtype, prec, 30, (hipStream_t)stream);
+    return subspace_diag_capped(c, psi, hpsi, eig, nblk, B, dtype, prec, 30, nblk * B, (hipStream_t)stream);
 }
 

@@ -672,6 +672,30 @@ jacobi_sort_kernel(const double *__restrict__ diag, const double *__restrict__ V
     }
 }
 
+// Padded states (index >= n of an N x N matrix): identity on their
+// diagonal, so Cholesky and the eigensolver leave them untouched.
+__global__ void pad_identity_kernel(double *__restrict__ S, int N, int n) {
+    const int i = n + blockIdx.x * 256 + threadIdx.x;
+    if (i < N) S[(int64_t)i * N + i] = 1.0;
+}
+
+// Leading n x n block of an N x N matrix, compacted to stride n.
+__global__ void compact_kernel(const double *__restrict__ A, int N, int n, double *__restrict__ Ac) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * n) return;
+    Ac[e] = A[(int64_t)(e / n) * N + e % n];
+}
+
+// V (N x N) = diag(Vc (n x n), identity); evals beyond n set to zero.
+__global__ void expand_kernel(const double *__restrict__ Vc, int n, int N, double *__restrict__ V,
+                              double *__restrict__ evals) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= N * N) return;
+    const int i = e / N, j = e % N;
+    V[e] = (i < n && j < n) ? Vc[i * n + j] : (i == j ? 1.0 : 0.0);
+    if (e >= n && e < N) evals[e] = 0.0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
@@ -846,6 +870,29 @@ rs_status dense_work_init(DenseWork &w, int64_t np, int max_states) {
     if (!s) s = w.rot.alloc((size_t)kMaxSweeps * (M - 1) * (M / 2) * sizeof(double2));
     (void)np;
     return s;
+}
+
+}  // namespace rs
+
+namespace rs {
+
+rs_status pad_identity(double *S, int N, int n, hipStream_t st) {
+    if (n >= N) return RS_OK;
+    hipLaunchKernelGGL(pad_identity_kernel, dim3((N - n + 255) / 256), dim3(256), 0, st, S, N, n);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+rs_status eigh_leading(DenseWork &w, double *A, double *V, double *evals, int N, int n, double *scratch_a,
+                       double *scratch_v, hipStream_t st, int max_sweeps) {
+    if (n >= N) return eigh(w, A, V, evals, N, st, max_sweeps);
+    hipLaunchKernelGGL(compact_kernel, dim3((n * n + 255) / 256), dim3(256), 0, st, A, N, n, scratch_a);
+    RS_HIP(hipGetLastError());
+    rs_status e = eigh(w, scratch_a, scratch_v, evals, n, st, max_sweeps);
+    if (e) return e;
+    hipLaunchKernelGGL(expand_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, scratch_v, n, N, V, evals);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
 }
 
 }  // namespace rs

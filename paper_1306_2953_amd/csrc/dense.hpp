@@ -38,5 +38,11 @@ rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStrea
 // 30) bounds the work (30 reaches full FP64 accuracy from any start).
 rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st,
                int max_sweeps = 30);
+// Padded states n..N-1 (all zero): S[i][i] = 1 for i >= n.
+rs_status pad_identity(double *S, int N, int n, hipStream_t st);
+// Eigenpairs of the leading n x n block of A (N x N); V = diag(V_n, I),
+// evals[n..N) = 0.  scratch_a, scratch_v: n*n doubles each.
+rs_status eigh_leading(DenseWork &w, double *A, double *V, double *evals, int N, int n, double *scratch_a,
+                       double *scratch_v, hipStream_t st, int max_sweeps);
 
 }  // namespace rs

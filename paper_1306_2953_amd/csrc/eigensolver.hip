@@ -25,7 +25,9 @@
 #include "internal.hpp"
 
 rs_status subspace_diag_capped(rs_ctx *c, void *psi, void *hpsi, double *eig, int nblk, int B, int dtype,
-                               int prec, int max_sweeps, hipStream_t st);
+                               int prec, int max_sweeps, int nreal, hipStream_t st);
+rs_status orthonormalize_impl(rs_ctx *c, void *psi, int nblk, int B, int dtype, int prec, double *S_out,
+                              int32_t *info, int nreal, hipStream_t s);
 
 namespace rs {
 rs_status hpsi_apply(const rs_grid *g, const rs_nl *nl, const void *vloc, const void *psi, void *hpsi,
@@ -270,7 +272,8 @@ __global__ void lambda_kernel(const double *__restrict__ d2, const double *__res
 __global__ void eps_kernel(const double *__restrict__ d2, int N, double *__restrict__ eps_out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
-    eps_out[c] = d2[1 * N + c] / d2[0 * N + c];
+    const double nn = d2[0 * N + c];
+    eps_out[c] = nn > 0.0 ? d2[1 * N + c] / nn : 0.0;     // zero (padding) states: 0
 }
 
 // DIIS coefficients per state (c_0 = 1); frozen or degenerate -> e_0.
@@ -301,7 +304,8 @@ __global__ void diis_kernel(const double *__restrict__ mats, int n, const double
 __global__ void sigma_kernel(const double *__restrict__ d2, int N, double *__restrict__ sigma) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
-    sigma[c] = -d2[1 * N + c] / d2[0 * N + c];
+    const double nn = d2[0 * N + c];
+    sigma[c] = nn > 0.0 ? -d2[1 * N + c] / nn : 0.0;
 }
 
 // Keep the learned direction d where <r|d> (rd[N + c]) is positive and
@@ -338,6 +342,7 @@ struct rs_solver {
     const rs_nl *nl = nullptr;
     const void *vloc = nullptr;
     int N = 0, B = 0, nblk = 0, dtype = 0, prec = 0;
+    int nreal = 0;                  // states asked for; N - nreal zero padding states
     rs_solver_opts opts{};
     rs_ctx *ctx = nullptr;
     size_t field_bytes = 0;
@@ -355,18 +360,19 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (!g || !vloc || !out) return fail(RS_EINVAL, "rs_eigensolve_create: null argument");
     *out = nullptr;
     if (B < 1 || B > 64 || (B & (B - 1))) return fail(RS_EINVAL, "rs_eigensolve_create: bad B");
-    if (nstates < 1 || nstates % B || nstates > 256)
-        return fail(RS_EINVAL, "rs_eigensolve_create: nstates must be a multiple of B in [1, 256]");
+    if (nstates < 1 || nstates > 256) return fail(RS_EINVAL, "rs_eigensolve_create: nstates must be in [1, 256]");
     if (dtype != RS_F64 && dtype != RS_F32) return fail(RS_EINVAL, "rs_eigensolve_create: bad dtype");
-    if (nl && nl->max_states < nstates) return fail(RS_EINVAL, "rs_eigensolve_create: projector set too small");
+    if (nl && nl->max_states < (nstates + B - 1) / B * B)
+        return fail(RS_EINVAL, "rs_eigensolve_create: projector set too small (needs whole blocks)");
     auto s = new (std::nothrow) rs_solver();
     if (!s) return fail(RS_ENOMEM, "host allocation failed");
     s->g = g;
     s->nl = nl;
     s->vloc = vloc;
-    s->N = nstates;
+    s->nblk = (nstates + B - 1) / B;
+    s->N = s->nblk * B;               // the last block is padded with zero states
+    s->nreal = nstates;
     s->B = B;
-    s->nblk = nstates / B;
     s->dtype = dtype;
     s->prec = dtype == RS_F64 ? RS_PREC_NATIVE : RS_PREC_BF16X3;
     rs_solver_opts o;
@@ -378,11 +384,11 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (opts) o = *opts;
     if (o.m < 1 || o.m > kMaxHist - 1) { delete s; return fail(RS_EINVAL, "rs_eigensolve_create: m must be 1..3"); }
     s->opts = o;
-    rs_status st = rs_ctx_create(g, nstates, &s->ctx);
+    rs_status st = rs_ctx_create(g, s->N, &s->ctx);
     if (st) { delete s; return st; }
     const size_t es = dtype == RS_F64 ? 8 : 4;
-    s->field_bytes = (size_t)g->np * nstates * es;
-    const int N = nstates;
+    s->field_bytes = (size_t)g->np * s->N * es;
+    const int N = s->N;
     const int nchunks = (int)((g->np + rsred::kChunk - 1) / rsred::kChunk);
     for (int i = 0; i <= o.m && !st; ++i) {   // iterate 0 is the caller's psi
         if (i > 0) st = s->hx[i].alloc(s->field_bytes);
@@ -457,7 +463,8 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     rs_status e;
     // 1. H psi, Rayleigh-Ritz
     if ((e = hpsi_apply(g, S->nl, S->vloc, psi, h0, nblk, B, S->dtype, st))) return e;
-    if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, kSweeps, st)))
+    if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, kSweeps,
+                                  S->nreal, st)))
         return e;
     // shifts for the learned preconditioner: sigma = -<psi|T psi>
     if (S->cnn || S->opts.record) {
@@ -543,17 +550,18 @@ extern "C" rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, do
     rs_status e = s->dtype == RS_F64 ? step_impl<double>(s, (double *)psi, st) : step_impl<float>(s, (float *)psi, st);
     if (e) return e;
     int32_t info = 0;
-    e = rs_orthonormalize_block(s->ctx, psi, s->nblk, s->B, s->dtype, s->prec, nullptr, &info, st);
-    std::vector<double> ev(s->N), rn(s->N);
-    RS_HIP(hipMemcpyAsync(ev.data(), s->eig.p, sizeof(double) * s->N, hipMemcpyDeviceToHost, st));
-    RS_HIP(hipMemcpyAsync(rn.data(), s->res.p, sizeof(double) * s->N, hipMemcpyDeviceToHost, st));
+    e = orthonormalize_impl(s->ctx, psi, s->nblk, s->B, s->dtype, s->prec, nullptr, &info, s->nreal, st);
+    const int n = s->nreal;
+    std::vector<double> ev(n), rn(n);
+    RS_HIP(hipMemcpyAsync(ev.data(), s->eig.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    RS_HIP(hipMemcpyAsync(rn.data(), s->res.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
-    if (eig) std::memcpy(eig, ev.data(), sizeof(double) * s->N);
-    if (resnorm) std::memcpy(resnorm, rn.data(), sizeof(double) * s->N);
+    if (eig) std::memcpy(eig, ev.data(), sizeof(double) * n);
+    if (resnorm) std::memcpy(resnorm, rn.data(), sizeof(double) * n);
     int c = 0;
-    for (int k = 0; k < s->N; ++k) c += rn[k] < s->opts.tol;
+    for (int k = 0; k < n; ++k) c += rn[k] < s->opts.tol;
     if (nconv) *nconv = c;
-    for (int k = 0; k < s->N; ++k)
+    for (int k = 0; k < n; ++k)
         if (!std::isfinite(ev[k]) || !std::isfinite(rn[k]))
             return fail(RS_ENONFINITE, "rs_eigensolve_step: non-finite eigenvalue or residual");
     s->steps++;

@@ -23,7 +23,7 @@ def _setup(w, N, B, dtype=np.float64, **kw):
     g = rsd.Grid.for_workload(w)
     nl = None
     if atoms is not None:
-        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=N)
+        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=-(-N // B) * B)
     v = torch.from_numpy(H.vloc.astype(dtype)).to(DEV)
     solver = rsd.Eigensolver(g, nl, v, N, B, **kw)
     psi = synthetic.draw_states(synthetic.rng_after_atoms(w), N, og.np)
@@ -93,3 +93,44 @@ def test_converges_dense_bruteforce(dtype, etol):
         if best < etol / 10:
             break
     assert best < etol
+
+
+def test_partial_last_block_step_matches_oracle():
+    """12 states in blocks of 8: the last block holds 4 zero padding states.
+    The step agrees with the oracle's on the 12 states (whose stopping rule
+    sees a block of 4), and the padding stays exactly zero."""
+    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    N, B = 12, 8
+    og, H, g, solver, psi = _setup(w, N, B, tol=1e-12)
+    opts = rmmdiis.Options(m=3, block=B, tol=1e-12)
+    for _ in range(3):
+        psi = rmmdiis.rmmdiis_step(H, psi, opts)["psi"]
+    want = rmmdiis.rmmdiis_step(H, psi, opts)
+    t = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
+    assert tuple(t.shape) == (2, og.np, B)
+    eig, res, nconv = solver.step(t)
+    assert eig.shape == (N,) and res.shape == (N,)
+    full = rsd.from_blocks(t.cpu().numpy())
+    assert np.all(full[N:] == 0.0)
+    got = full[:N]
+    assert np.max(np.abs(eig - want["eig"])) < 1e-10 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-8 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-7 * np.max(np.abs(want["psi"]))
+
+
+@pytest.mark.parametrize("dtype,etol", [(np.float64, 1e-10), (np.float32, 1e-6)])
+def test_partial_last_block_converges(dtype, etol):
+    """6 states in blocks of 4 (two padding states) reach the lowest six
+    eigenvalues of the dense matrix of a tiny sphere."""
+    w = synthetic.make_config(2, radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
+    og, H, g, solver, psi = _setup(w, 6, 4, dtype=dtype, tol=1e-9 if dtype == np.float64 else 1e-5)
+    ev = np.linalg.eigvalsh(H.dense())[:6]
+    t = torch.from_numpy(rsd.to_blocks(psi.astype(dtype), 4)).to(DEV)
+    best = np.inf
+    for it in range(300):
+        eig, res, nconv = solver.step(t)
+        best = np.max(np.abs(eig - ev))
+        if best < etol / 10:
+            break
+    assert best < etol
+    assert np.all(rsd.from_blocks(t.cpu().numpy())[6:] == 0.0)

@@ -138,6 +138,30 @@ def test_full_size_sphere_sampled(dtype, tol):
     assert _relerr(got[:, pts], want) < tol
 
 
+@pytest.mark.parametrize("cfg,N,B", [(4, 64, 32), (5, 64, 64)])
+def test_full_size_periodic_and_cage_sampled(cfg, N, B):
+    """Config 4 (periodic 96^3, 32 atoms, minimum image) and config 5 (sphere
+    R 18 at h 0.18, 4.19M points, 60 atoms on a cage) in FP32, N states,
+    checked at sampled points (grid-wide and inside projector spheres)."""
+    w = synthetic.CONFIGS[cfg]
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    assert g.np == og.np
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=N)
+    psi = _states(w, N, og.np, np.float32)
+    v = H.vloc.astype(np.float32)
+    got = _gpu_hpsi(g, nl, v, psi, B, np.float32)
+    x64 = psi.astype(np.float64)
+    rng = np.random.default_rng(cfg)
+    pts = rng.choice(og.np, 300, replace=False)
+    sph = np.concatenate(H.proj.idx)
+    pts = np.unique(np.concatenate([pts, rng.choice(sph, 200, replace=False)]))
+    want = stencil.apply_local_at(og, v.astype(np.float64), x64, pts)
+    P = kb.project(H.proj, x64)
+    want += kb.apply_projections(H.proj, P, og.np)[:, pts]
+    assert _relerr(got[:, pts], want) < 1e-5
+
+
 def test_bad_block_size_rejected():
     og, H, g, nl = _system(SMALL)
     t = torch.zeros((1, og.np, 3), dtype=torch.float64, device=DEV)
