@@ -57,6 +57,23 @@ template <typename T> struct OpDots2 {   // <x|x>, <x|y>
         a[1] += u * v;
     }
 };
+// y = x + lambda d, hy = hx + lambda hd (per-state lambda; in place when
+// y == x), and the dots <y|y>, <y|hy> of the new iterate for its Rayleigh
+// quotient.
+template <typename T> struct OpAxpy2Dots {
+    const T *x, *hx, *d, *hd;
+    T *y, *hy;
+    const double *lam;
+    __device__ void operator()(int64_t i, int c, double *a) const {
+        const double l = lam[c];
+        const T yv = (T)((double)x[i] + l * (double)d[i]);
+        const T hv = (T)((double)hx[i] + l * (double)hd[i]);
+        y[i] = yv;
+        hy[i] = hv;
+        a[0] += (double)yv * (double)yv;
+        a[1] += (double)yv * (double)hv;
+    }
+};
 template <typename T> struct OpResid {   // R = h - eps x, <R|R>
     const T *x, *h;
     T *R;
@@ -109,17 +126,15 @@ template <typename T, int NIT> struct OpDiis {
 };
 
 // --------------------------------------------------------- map kernels
-// y = x + lambda d, hy = hx + lambda hd (per-state lambda)
+// y = x + lambda d (the newest iterate, written straight into psi)
 template <typename T>
 __global__ void __launch_bounds__(256)
-axpy2_kernel(const T *__restrict__ x, const T *__restrict__ hx, const T *__restrict__ d, const T *__restrict__ hd,
-             T *__restrict__ y, T *__restrict__ hy, const double *__restrict__ lam, int64_t np, int B, int64_t total) {
+axpy1_kernel(const T *__restrict__ x, const T *__restrict__ d, T *y, const double *__restrict__ lam, int64_t np,
+             int B, int64_t total) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
     const int c = (int)(i / (np * B)) * B + (int)(i % B);
-    const double l = lam[c];
-    y[i] = (T)((double)x[i] + l * (double)d[i]);
-    hy[i] = (T)((double)hx[i] + l * (double)hd[i]);
+    y[i] = (T)((double)x[i] + lam[c] * (double)d[i]);
 }
 
 // psi_bar = sum_a c_a e_a, H psi_bar = sum_a c_a he_a, R_bar = sum_a c_a r_a
@@ -494,14 +509,23 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     const T *xs[kMaxHist], *hs[kMaxHist];
     xs[0] = psi;
     hs[0] = h0;
-    hipLaunchKernelGGL(axpy2_kernel<T>, dim3(gm), dim3(256), 0, st, psi, h0, S->d.as<T>(), S->hd.as<T>(),
-                       S->hx[1].as<T>(), S->hh[1].as<T>(), S->lam.as<double>(), np, B, total);
+    if (m == 1) {
+        // the trial iterate is the newest: straight into psi (in place)
+        hipLaunchKernelGGL(axpy1_kernel<T>, dim3(gm), dim3(256), 0, st, psi, S->d.as<T>(), psi,
+                           S->lam.as<double>(), np, B, total);
+        RS_HIP(hipGetLastError());
+        return RS_OK;
+    }
+    // iterate 1 and its dots [<x|x>, <x|Hx>] in one pass
+    if ((e = colreduce<2>(OpAxpy2Dots<T>{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->hx[1].as<T>(),
+                                        S->hh[1].as<T>(), S->lam.as<double>()},
+                          np, B, nblk, dv, partial, S->d2.as<double>(), st)))
+        return e;
     xs[1] = S->hx[1].as<T>();
     hs[1] = S->hh[1].as<T>();
     for (int n = 2; n <= m; ++n) {
         // 4. DIIS iteration over the n iterates 0..n-1: eps of the newest
-        if ((e = colreduce<2>(OpDots2<T>{xs[n - 1], hs[n - 1]}, np, B, nblk, dv, partial, S->d2.as<double>(), st)))
-            return e;
+        // (its dots were accumulated when it was written)
         hipLaunchKernelGGL(eps_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N,
                            S->eps.as<double>() + (int64_t)(n - 1) * N);
         if (n == 2) {
@@ -529,13 +553,19 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
         RS_HIP(hipGetLastError());
         if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
         if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
-        hipLaunchKernelGGL(axpy2_kernel<T>, dim3(gm), dim3(256), 0, st, xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb,
-                           S->lam.as<double>(), np, B, total);
+        if (n < m) {
+            if ((e = colreduce<2>(OpAxpy2Dots<T>{xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb, S->lam.as<double>()},
+                                  np, B, nblk, dv, partial, S->d2.as<double>(), st)))
+                return e;
+        } else {
+            // the newest iterate goes straight into psi (frozen states: it
+            // equals psi); its H psi is not needed
+            hipLaunchKernelGGL(axpy1_kernel<T>, dim3(gm), dim3(256), 0, st, xb, S->d.as<T>(), psi,
+                               S->lam.as<double>(), np, B, total);
+        }
         xs[n] = xb;
         hs[n] = hb;
     }
-    // newest iterate back into psi (frozen states: it equals psi)
-    RS_HIP(hipMemcpyAsync(psi, xs[m], S->field_bytes, hipMemcpyDeviceToDevice, st));
     RS_HIP(hipGetLastError());
     return RS_OK;
 }

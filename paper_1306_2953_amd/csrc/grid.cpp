@@ -178,9 +178,20 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
                 fast = r.nbr[f] >= 0 && g->bricks_host[r.nbr[f]].mask == ~0ull;
             r.flags = fast ? kBrickFast : 0;
         }
-        // execution order: bricks sorted along a Z-order (Morton) curve of
-        // their lattice coordinates, so that bricks processed together are
-        // spatially compact and their neighbours stay in cache
+        // execution order: z-pencils of 8 x 8 bricks in x-y, the pencils
+        // along a 2-D Z-order (Morton) curve, each pencil from low to high z,
+        // a Morton curve inside each z layer of a pencil.  Bricks processed
+        // together are then spatially compact and a brick's z neighbours are
+        // processed just before and after it, while its neighbours are still
+        // in L2 (RS_EXEC_PENCIL 0: a plain 3-D Morton curve).
+#ifndef RS_EXEC_PENCIL
+#define RS_EXEC_PENCIL 1
+#endif
+        auto spread = [](uint64_t v, int stride) {
+            uint64_t m = 0;
+            for (int bit = 0; bit < 21; ++bit) m |= ((v >> bit) & 1) << (stride * bit);
+            return m;
+        };
         std::vector<std::pair<uint64_t, int32_t>> key;
         key.reserve(nbricks);
         for (int64_t bz = 0; bz < nbz; ++bz)
@@ -188,11 +199,13 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
                 for (int64_t bx = 0; bx < nbx; ++bx) {
                     const int32_t b = g->brick_map[(bz * nby + by) * nbx + bx];
                     if (b < 0) continue;
-                    uint64_t m = 0;
-                    for (int bit = 0; bit < 21; ++bit) {
-                        m |= (uint64_t)((bx >> bit) & 1) << (3 * bit);
-                        m |= (uint64_t)((by >> bit) & 1) << (3 * bit + 1);
-                        m |= (uint64_t)((bz >> bit) & 1) << (3 * bit + 2);
+                    uint64_t m;
+                    if (RS_EXEC_PENCIL) {
+                        const uint64_t tile = spread(bx >> 3, 2) | (spread(by >> 3, 2) << 1);
+                        const uint64_t inner = spread(bx & 7, 2) | (spread(by & 7, 2) << 1);
+                        m = (tile << 40) | ((uint64_t)bz << 8) | inner;
+                    } else {
+                        m = spread(bx, 3) | (spread(by, 3) << 1) | (spread(bz, 3) << 2);
                     }
                     key.emplace_back(m, b);
                 }
