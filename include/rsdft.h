@@ -283,6 +283,12 @@ void rs_eigensolve_destroy(rs_solver *s);
 rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, double *resnorm,
                              int32_t *nconv, void *stream);
 
+/* Orthonormalises the solver's states in psi (eq. (8), as at the end of a
+ * step), leaving the padding states of a partial last block zero: the
+ * starting point of rs_eigensolve_step.  Synchronises.  RS_ENOTPOSDEF when
+ * the states are linearly dependent. */
+rs_status rs_eigensolve_orthonormalize(rs_solver *s, void *psi, void *stream);
+
 /* ------------------------------------------- learned preconditioner
  * Not from the paper: its RMM-DIIS step (Sec. 3) leaves the preconditioner
  * open and uses a filter; this replaces the filter by a small network

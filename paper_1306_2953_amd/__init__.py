@@ -306,6 +306,10 @@ class Eigensolver:
             res.ctypes.data_as(_abi.PF64), ctypes.byref(nconv), _stream(stream)))
         return eig, res, nconv.value
 
+    def orthonormalize(self, psi, stream=None):
+        """Orthonormalise the states (padding states stay zero)."""
+        check(lib().rs_eigensolve_orthonormalize(self._h, _dev(psi, "psi"), _stream(stream)))
+
     def set_precond(self, cnn: Optional["Cnn"]):
         """Use the network as preconditioner (None: the filter)."""
         check(lib().rs_eigensolve_set_precond(self._h, cnn.handle if cnn is not None else None))

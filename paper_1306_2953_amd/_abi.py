@@ -63,6 +63,7 @@ SIGNATURES = {
     "rs_eigensolve_destroy": (None, [P]),
     "rs_eigensolve_step": (ctypes.c_int, [P, P, PF64, PF64, PI32, P]),
     "rs_eigensolve_set_precond": (ctypes.c_int, [P, P]),
+    "rs_eigensolve_orthonormalize": (ctypes.c_int, [P, P, P]),
     "rs_eigensolve_residuals": (ctypes.c_int, [P, P, P, P]),
     "rs_cnn_create": (ctypes.c_int, [I32, I64, ctypes.POINTER(P)]),
     "rs_cnn_destroy": (None, [P]),

@@ -613,3 +613,10 @@ extern "C" rs_status rs_eigensolve_residuals(rs_solver *s, void *R, double *sigm
     RS_HIP(hipMemcpyAsync(sigma, s->sigma.p, sizeof(double) * s->N, hipMemcpyDeviceToDevice, st));
     return RS_OK;
 }
+
+extern "C" rs_status rs_eigensolve_orthonormalize(rs_solver *s, void *psi, void *stream) {
+    if (!s || !psi) return rs::fail(RS_EINVAL, "rs_eigensolve_orthonormalize: null argument");
+    int32_t info = 0;
+    return orthonormalize_impl(s->ctx, psi, s->nblk, s->B, s->dtype, s->prec, nullptr, &info, s->nreal,
+                               (hipStream_t)stream);
+}

@@ -134,3 +134,35 @@ def test_partial_last_block_converges(dtype, etol):
             break
     assert best < etol
     assert np.all(rsd.from_blocks(t.cpu().numpy())[6:] == 0.0)
+
+
+def test_cage_workload_full_size_steps():
+    """The largest workload (sphere R 18 at h 0.18, 4.19M points, 60 atoms on
+    a cage), 240 FP32 states in blocks of 64 (one padded block): three steps
+    run, keep the padding zero, and lower every Rayleigh-Ritz value."""
+    w = synthetic.CONFIGS[5]
+    g = rsd.Grid.for_workload(w)
+    atoms = synthetic.draw_atoms(w)
+    v = synthetic.potential_for(w, g.xyz(), atoms)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=256)
+    tv = torch.from_numpy(v.astype(np.float32)).to(DEV)
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np).astype(np.float32)
+    t = torch.from_numpy(rsd.to_blocks(psi, w.block)).to(DEV)
+    del psi
+    assert tuple(t.shape) == (4, g.np, 64)
+    solver = rsd.Eigensolver(g, nl, tv, w.nstates, w.block)
+    solver.orthonormalize(t)
+    eigs = [solver.step(t)[0] for _ in range(3)]
+    assert all(e.shape == (240,) and np.all(np.isfinite(e)) for e in eigs)
+    assert np.all(eigs[2] <= eigs[0] + 1e-6 * np.abs(eigs[0]))
+    assert torch.count_nonzero(t[3, :, 48:]).item() == 0
+
+
+def test_bad_solver_arguments_raise():
+    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    g = rsd.Grid.for_workload(w)
+    v = torch.zeros(g.np, dtype=torch.float64, device=DEV)
+    for n, B in ((0, 8), (257, 8), (16, 3), (16, 128)):
+        with pytest.raises(rsd.RsError) as e:
+            rsd.Eigensolver(g, None, v, n, B)
+        assert e.value.code == rsd._abi.RS_EINVAL
