@@ -171,6 +171,11 @@ def _counter_means(path, counter):
     return {k: sum(v) / len(v) for k, v in per.items()}
 
 
+# the kernels of one H psi call besides the projections: the z-marching
+# stencil (FP64) or the per-brick stencil (FP32), and the projector add
+STENCIL_KERNELS = ("hpsi_march_kernel", "hpsi_brick_kernel", "nl_add_kernel")
+
+
 def traffic_record(w, dtype, fetch_csv, write_csv):
     """Calibrated HBM bytes per H psi call of the stencil kernel (interior
     and surface launches): counted KiB x (1 GiB / the KiB the counter shows
@@ -182,7 +187,7 @@ def traffic_record(w, dtype, fetch_csv, write_csv):
         if not cal:
             raise SystemExit(f"no calibration kernel in {path}")
         factor = float(1 << 30) / (cal[0] * 1024.0)
-        kib = sum(v for k, v in m.items() if "hpsi_brick_kernel" in k)
+        kib = sum(v for k, v in m.items() if any(n in k for n in STENCIL_KERNELS))
         out[key] = dict(counted_kib=kib, calibration_kib_per_gib=cal[0], bytes=kib * 1024.0 * factor)
     path = os.path.join(ROOT, "profiles", "hpsi_traffic.json")
     try:
@@ -454,7 +459,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": r["frac"],
                      "traffic": measured_traffic(w.name, dtype),
-                     "kernel": "hpsi_brick_kernel (interior + surface launches of one call)",
+                     "kernel": ("hpsi_march_kernel (full + partial chunk launches) + nl_add_kernel, "
+                                "one H psi call" if dtype == "f64" else
+                                "hpsi_brick_kernel (interior + surface launches), one H psi call"),
                      "bytes_per_launch": r["bytes_kernel"],
                      "avg_launch_s": r["t_kernel"]},
         "eigensolve": eig,

@@ -219,9 +219,83 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
             }
         g->nfast = 0;
         for (int64_t b = 0; b < nbricks; ++b) g->nfast += (g->bricks_host[b].flags & kBrickFast) != 0;
+        // z-marching chunks: tiles of 2 x 2 bricks; each tile's occupied z
+        // range cut at a global grid of kMarchCZ-layer bands (chunk ends at
+        // multiples of 3 layers, the kernel's unrolled step of 12 planes), so
+        // that the chunks of neighbouring tiles cover the same layers and,
+        // run together, share their x-y neighbour rows in L2.  Order: band,
+        // then the tiles along a 2-D Morton curve.  Table layers: bz0-1 ..
+        // bz0+nz, then one absent layer (the kernel's last prefetches read it).
+        const bool per = d->kind == RS_GRID_PERIODIC;
+        auto wrap = [](int64_t v, int64_t n) { return ((v % n) + n) % n; };
+        std::vector<MarchBrick> mtab;
+        std::vector<std::pair<uint64_t, MarchChunk>> mfull, mpart;
+        const int64_t ntx = (nbx + 1) / 2, nty = (nby + 1) / 2;
+        static const int pdx[12] = {0, 1, 0, 1, -1, -1, 2, 2, 0, 1, 0, 1};
+        static const int pdy[12] = {0, 0, 1, 1, 0, 1, 0, 1, -1, -1, 2, 2};
+        static_assert(kMarchCZ % 3 == 0, "bands are whole groups of 3 layers");
+        for (int64_t ty = 0; ty < nty; ++ty)
+            for (int64_t tx = 0; tx < ntx; ++tx) {
+                int64_t zmin = nbz, zmax = -1;
+                for (int64_t bz = 0; bz < nbz; ++bz)
+                    for (int o = 0; o < 4; ++o) {
+                        const int64_t bx = 2 * tx + pdx[o], by = 2 * ty + pdy[o];
+                        if (bx < nbx && by < nby && g->brick_map[(bz * nby + by) * nbx + bx] >= 0) {
+                            zmin = std::min(zmin, bz);
+                            zmax = std::max(zmax, bz);
+                        }
+                    }
+                if (zmax < 0) continue;
+                const int64_t lo3 = zmin / 3 * 3, hi3 = (zmax / 3 + 1) * 3;   // [lo3, hi3): whole triples
+                for (int64_t band = lo3 / kMarchCZ; band * kMarchCZ < hi3; ++band) {
+                    const int64_t bz0 = std::max(lo3, band * (int64_t)kMarchCZ);
+                    const int nz = (int)(std::min(hi3, (band + 1) * (int64_t)kMarchCZ) - bz0);
+                    MarchChunk mc{(int32_t)mtab.size(), nz};
+                    bool full = true;
+                    for (int l = 0; l < nz + 3; ++l) {
+                        const int64_t bz = bz0 - 1 + l;
+                        for (int pos = 0; pos < 12; ++pos) {
+                            int64_t bx = 2 * tx + pdx[pos], by = 2 * ty + pdy[pos], bzz = bz;
+                            // a tile brick is written by this chunk when it is
+                            // one of the chunk's layers and inside the lattice
+                            const bool owned = pos < 4 && bx < nbx && by < nby && l >= 1 && l <= nz &&
+                                               bz >= zmin && bz <= zmax;
+                            int32_t id = -1;
+                            if (l == nz + 2) {
+                                id = -1;
+                            } else if (per) {
+                                bx = wrap(bx, nbx); by = wrap(by, nby); bzz = wrap(bzz, nbz);
+                                id = g->brick_map[(bzz * nby + by) * nbx + bx];
+                            } else if (bx >= 0 && bx < nbx && by >= 0 && by < nby && bzz >= 0 && bzz < nbz) {
+                                id = g->brick_map[(bzz * nby + by) * nbx + bx];
+                            }
+                            MarchBrick mb{0, 0, -1};
+                            if (id >= 0) {
+                                mb.mask = g->bricks_host[id].mask;
+                                mb.start = g->bricks_host[id].start;
+                                mb.id = owned ? id : -1;
+                            }
+                            if (l <= nz + 1 && (mb.mask != ~0ull || (pos < 4 && l >= 1 && l <= nz && mb.id < 0)))
+                                full = false;
+                            mtab.push_back(mb);
+                        }
+                    }
+                    const uint64_t key = ((uint64_t)band << 44) | spread(tx, 2) | (spread(ty, 2) << 1);
+                    (full ? mfull : mpart).emplace_back(key, mc);
+                }
+            }
+        std::sort(mfull.begin(), mfull.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+        std::sort(mpart.begin(), mpart.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+        std::vector<MarchChunk> mch;
+        for (auto &e : mfull) mch.push_back(e.second);
+        for (auto &e : mpart) mch.push_back(e.second);
+        g->nmarch = (int64_t)mch.size();
+        g->nmarch_full = (int64_t)mfull.size();
         if (!g->host_only) {
             rs_status st = g->bricks.upload(g->bricks_host);
             if (!st) st = g->exec.upload(order);
+            if (!st) st = g->march_chunk.upload(mch);
+            if (!st) st = g->march_tab.upload(mtab);
             if (st) { delete g; return st; }
         }
     }

@@ -11,6 +11,11 @@
 // per output and no neighbour table (the brick's 64-bit occupancy mask and
 // first-point index locate every point).  Points outside the domain are zero
 // and cost no memory traffic.
+//
+// FP64 uses a second design, hpsi_march_kernel below: work-groups march
+// through 8 x 8-point columns in z with a register window along z and the
+// x-y neighbours staged in LDS, which cuts the row reads per output from
+// 9-13 to about 3.
 #include "internal.hpp"
 
 namespace rs {
@@ -353,6 +358,310 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
 #undef RS_PART
 }
 
+// ---------------------------------------------------------------------------
+// z-marching kernel (the 25-point stencil of Sec. 5.1 plus the local
+// potential; the projector term is added by nl_add_kernel).  A work-group
+// owns one chunk: a column of 2 x 2 bricks (8 x 8 points in x-y) over nz
+// brick layers, for one group of SG state columns (SG * sizeof(T) = 128
+// bytes of each point row).  It walks the chunk plane by plane in z:
+//  - each thread owns PPT points (1, a 2 x 1 or a 2 x 2 block) of one state
+//    column and keeps the values of planes z-4 .. z+7 of those points in
+//    registers, so the z part of the stencil costs one load per output,
+//    issued three planes ahead;
+//  - the plane's 8 x 8 points and their x/y neighbours (4 deep on each side,
+//    128 points) are staged in LDS as a 16 x 16-point plane of 128-byte rows;
+//    the neighbour rows are fetched two planes ahead as 16-byte pieces.  Two
+//    LDS planes alternate, so one barrier per plane suffices.
+// A chunk reads its own rows once, the 4 planes below and above it, and
+// each plane's 128 x-y neighbour points, which the chunks of neighbouring
+// tiles in the same band (run at the same time on the same XCD) have just
+// brought into L2.  The step is unrolled over the 12 slots of the register
+// window (chunks are whole groups of 12 planes), so every ring index is a
+// compile-time constant and no load sits under a branch.
+constexpr int kMW = 12;   // register window planes
+
+// Measured choices for the z-marching kernel: 128-byte state groups (64:
+// two work-groups per CU, but slower), FP64 one point per thread (1024
+// threads, 4 waves per SIMD; 2 and 4 points cost occupancy) in the plain
+// form, FP32 on the per-brick kernel (RS_MARCH_F32 1 runs it here, 2 points
+// per thread, first-difference form).
+#ifndef RS_MARCH_PLAIN64
+#define RS_MARCH_PLAIN64 1
+#endif
+#ifndef RS_MARCH_RB
+#define RS_MARCH_RB 128
+#endif
+#ifndef RS_MARCH_F32
+#define RS_MARCH_F32 0
+#endif
+#ifndef RS_MARCH_PPT32
+#define RS_MARCH_PPT32 2
+#endif
+#ifndef RS_MARCH_PPT64
+#define RS_MARCH_PPT64 1
+#endif
+template <typename T, int B, int SG, int PPT, bool FULL>
+__global__ void __launch_bounds__((64 / PPT) * SG)
+hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__restrict__ tab, int nchunk,
+                  int nsg, int nwg_pad, const T *__restrict__ psi, T *__restrict__ hpsi, const T *__restrict__ vloc,
+                  T vconst, int64_t np, T pre, T w0, T w1, T w2, T w3) {
+    constexpr int NT = (64 / PPT) * SG;
+    constexpr int NI = PPT == 1 ? 1 : 2;         // the thread's points: NI x NJ in x-y
+    constexpr int NJ = PPT == 4 ? 2 : 1;
+    constexpr int RB = SG * (int)sizeof(T);
+    constexpr int ROWB = B * (int)sizeof(T);
+    constexpr int NPC = RB / 16;                 // 16-byte pieces of a point row
+    constexpr int KH = 128 * NPC / NT;           // neighbour pieces per thread and plane
+    constexpr int PLANE = 256 * RB;
+    constexpr int PH = 2;                        // planes of neighbour prefetch
+    constexpr bool PLAIN = sizeof(T) == 8 && RS_MARCH_PLAIN64;
+    static_assert(RB == 64 || RB == 128, "a state group is 64 or 128 bytes of a point row");
+    static_assert(PPT == 1 || PPT == 2 || PPT == 4, "1 x 1, 2 x 1 or 2 x 2 points per thread");
+    static_assert(KH >= 1 && 12 % PH == 0, "launch shape");
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * PLANE];
+    __shared__ MarchBrick ltab[(kMarchCZ + 3) * 12];
+
+    // work item: chunk wg % nchunk of state group wg / nchunk; each XCD runs
+    // a contiguous run of the chunk list (bands of z, tiles in Morton order),
+    // so the tiles it holds at once are neighbours at the same depth
+    const int wg = xcd_remap(blockIdx.x, nwg_pad);
+    if (wg >= nchunk * nsg) return;
+    const MarchChunk ch = chunks[wg % nchunk];
+    const int sg = wg / nchunk;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < (ch.nz + 3) * 12; i += NT) ltab[i] = tab[ch.tab + i];
+    __syncthreads();
+
+    // thread: state column s of the group, block of NI x NJ points at (x0, y0)
+    const int s = tid % SG, pg = tid / SG;
+    const int x0 = NI * (pg % (8 / NI)), y0 = NJ * (pg / (8 / NI));
+    const int opos = (x0 >> 2) + 2 * (y0 >> 2);
+    const int oq = (y0 & 3) * 4 + (x0 & 3);
+    const int blk = sg * SG / B, s0 = sg * SG % B;
+    const int64_t bel = np * B;
+    const rsrc_t rp = make_rsrc(psi + blk * bel, (uint32_t)(bel * sizeof(T)));
+    const rsrc_t rh = make_rsrc(hpsi + blk * bel, (uint32_t)(bel * sizeof(T)));
+    // without vloc every potential load reads past a zero-sized buffer (0)
+    const rsrc_t rv = make_rsrc(vloc, vloc ? (uint32_t)(np * sizeof(T)) : 0u);
+    const uint32_t loff = (uint32_t)((s0 + s) * sizeof(T));
+    const uint32_t hc = (uint32_t)(s0 * sizeof(T) + (tid % NPC) * 16);
+
+    // neighbour pieces: point hp of the 128 (32 rows of 4 points: 16 x-side
+    // rows, then 16 y-side rows), 16-byte piece tid % NPC of its row
+    int hpos[KH], hq[KH];
+    uint32_t hlds[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+        const int hp = (tid + k * NT) / NPC;
+        const int hr = hp >> 2, xi = hp & 3;
+        int X, Y;
+        if (hr < 16) {
+            const int side = hr >> 3, y = hr & 7;
+            hpos[k] = 4 + 2 * side + (y >> 2);
+            hq[k] = (y & 3) * 4 + xi;
+            X = side ? 12 + xi : xi;
+            Y = y + 4;
+        } else {
+            const int r = hr - 16, side = r >> 3, yv = (r & 7) >> 1, xb = r & 1;
+            hpos[k] = 8 + 2 * side + xb;
+            hq[k] = yv * 4 + xi;
+            X = 4 + 4 * xb + xi;
+            Y = side ? 12 + yv : yv;
+        }
+        hlds[k] = (uint32_t)((Y * 16 + X) * RB + (tid % NPC) * 16);
+    }
+
+    // point index of slot q of a table entry, or -1
+    auto prow = [&](const MarchBrick &mb, int q) -> int {
+        if constexpr (FULL) {
+            return mb.start + q;
+        } else {
+            const uint64_t m = mb.mask;
+            return ((m >> q) & 1ull) ? mb.start + __popcll(m & ((1ull << q) - 1ull)) : -1;
+        }
+    };
+    // byte offset of point r's row plus extra (full chunks: r is never -1)
+    auto roff = [&](int r, uint32_t extra, uint32_t rowb) -> uint32_t {
+        if constexpr (FULL) return (uint32_t)r * rowb + extra;
+        else return r < 0 ? kOOB : (uint32_t)r * rowb + extra;
+    };
+    // own point k: (x0 + k % NI, y0 + k / NI)
+    auto load_own = [&](int p, T (&w)[PPT]) {
+        const MarchBrick mb = ltab[(p >> 2) * 12 + opos];
+        const int q0 = (p & 3) * 16 + oq;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) w[k] = bload<T>(rp, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), loff, ROWB));
+    };
+    auto load_halo = [&](int p, u32x4 (&h)[KH]) {
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+            const MarchBrick mb = ltab[(p >> 2) * 12 + hpos[k]];
+            h[k] = __builtin_amdgcn_raw_buffer_load_b128(rp, (int)roff(prow(mb, (p & 3) * 16 + hq[k]), hc, ROWB), 0, 0);
+        }
+    };
+    auto load_v = [&](int p, T (&v)[PPT]) {
+        const MarchBrick mb = ltab[(p >> 2) * 12 + opos];
+        const int q0 = (p & 3) * 16 + oq;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            v[k] = bload<T>(rv, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), 0u, (uint32_t)sizeof(T)));
+    };
+
+    T win[kMW][PPT];
+    u32x4 hreg[PH][KH];
+    T vreg[3][PPT];
+    const int zend = 4 + 4 * ch.nz;            // output planes [4, zend) of the chunk's numbering
+
+    // prologue: window planes 0 .. 10, neighbours of planes 4 .. 3 + PH, V
+    // of planes 4 and 5
+#pragma unroll
+    for (int p = 0; p < 11; ++p) load_own(p, win[p]);
+#pragma unroll
+    for (int p = 4; p < 4 + PH; ++p) load_halo(p, hreg[p % PH]);
+    load_v(4, vreg[4 % 3]);
+    load_v(5, vreg[5 % 3]);
+
+    // one plane z = zb + K (zb = 4 mod 12)
+    auto step = [&](int zb, auto KC) {
+        constexpr int K = decltype(KC)::value;
+        const int z = zb + K;
+        // keep the steps apart: interleaving two planes' arithmetic costs
+        // registers (and occupancy)
+        __builtin_amdgcn_sched_barrier(0);
+        constexpr int c0 = (4 + K) % kMW;                 // window slot of plane z
+        constexpr int hs = (4 + K) % PH;                  // neighbour ring slot of plane z
+        constexpr int vs = (4 + K) % 3;                   // V ring slot of plane z
+        unsigned char *pl = lds + (K & 1) * PLANE;
+        // stage plane z: own values from the window, neighbours from the ring
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            *(T *)(pl + ((y0 + k / NI + 4) * 16 + x0 + k % NI + 4) * RB + s * sizeof(T)) = win[c0][k];
+#pragma unroll
+        for (int k = 0; k < KH; ++k) *(u32x4 *)(pl + hlds[k]) = hreg[hs][k];
+        // prefetch: window plane z + 7, neighbours of plane z + PH, V of z + 2
+        load_own(z + 7, win[(c0 + 7) % kMW]);
+        load_halo(z + PH, hreg[hs]);
+        load_v(z + 2, vreg[(vs + 2) % 3]);
+        __syncthreads();
+        const unsigned char *L = pl + (y0 * 16 + x0) * RB + s * sizeof(T);   // point (x0 - 4, y0 - 4)
+        auto at = [&](int dx, int dy) -> T { return *(const T *)(L + ((dy + 4) * 16 + dx + 4) * RB); };
+        T acc[PPT];
+        if constexpr (PLAIN) {
+            // FP64: the plain form c0 v + sum_m c_m (v_-m + v_+m) per axis, with
+            // c_m = W_(m-1) - W_m (W_4 = 0) and c0 = -2 W_0; no cancellation
+            // concern at this precision and about half the operations
+            const T c1 = w0 - w1, c2 = w1 - w2, c3 = w2 - w3, c4 = w3, c0x3 = T(-6) * w0;
+            const T cc[5] = {T(0), c1, c2, c3, c4};
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int i = k % NI, j = k / NI;
+                auto X = [&](int ii) -> T { return (ii >= 0 && ii < NI) ? win[c0][ii + NI * j] : at(ii, j); };
+                auto Y = [&](int jj) -> T { return (jj >= 0 && jj < NJ) ? win[c0][i + NI * jj] : at(i, jj); };
+                T sum = c0x3 * win[c0][k];
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) {
+                    sum += cc[m] * (X(i - m) + X(i + m));
+                    sum += cc[m] * (Y(j - m) + Y(j + m));
+                    sum += cc[m] * (win[(c0 + kMW - m) % kMW][k] + win[(c0 + m) % kMW][k]);
+                }
+                acc[k] = pre * sum + (vreg[vs][k] + vconst) * win[c0][k];
+            }
+        } else {
+        // x lines: the thread's NJ rows of NI points
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            T v[8 + NI], lap[NI];
+#pragma unroll
+            for (int m = 0; m < 8 + NI; ++m)
+                v[m] = (m >= 4 && m < 4 + NI) ? win[c0][(m - 4) + NI * j] : at(m - 4, j);
+            line_lap<T, 8 + NI, 4>(v, lap, w0, w1, w2, w3);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) acc[i + NI * j] = lap[i];
+        }
+        // y lines: NI columns of NJ points
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            T v[8 + NJ], lap[NJ];
+#pragma unroll
+            for (int m = 0; m < 8 + NJ; ++m)
+                v[m] = (m >= 4 && m < 4 + NJ) ? win[c0][i + NI * (m - 4)] : at(i, m - 4);
+            line_lap<T, 8 + NJ, 4>(v, lap, w0, w1, w2, w3);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[i + NI * j] += lap[j];
+        }
+        // z lines from the window, then the potential
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            T v[9], lap[1];
+#pragma unroll
+            for (int m = 0; m < 9; ++m) v[m] = win[(c0 + kMW - 4 + m) % kMW][k];
+            line_lap<T, 9, 4>(v, lap, w0, w1, w2, w3);
+            acc[k] = pre * (acc[k] + lap[0]) + (vreg[vs][k] + vconst) * win[c0][k];
+        }
+        }
+        const MarchBrick mb = ltab[(z >> 2) * 12 + opos];
+        const int q0 = (z & 3) * 16 + oq;
+        if (FULL || mb.id >= 0) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                bstore<T>(acc[k], rh, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), loff, ROWB));
+        }
+    };
+    for (int zb = 4; zb < zend; zb += kMW) {
+        step(zb, std::integral_constant<int, 0>{});
+        step(zb, std::integral_constant<int, 1>{});
+        step(zb, std::integral_constant<int, 2>{});
+        step(zb, std::integral_constant<int, 3>{});
+        step(zb, std::integral_constant<int, 4>{});
+        step(zb, std::integral_constant<int, 5>{});
+        step(zb, std::integral_constant<int, 6>{});
+        step(zb, std::integral_constant<int, 7>{});
+        step(zb, std::integral_constant<int, 8>{});
+        step(zb, std::integral_constant<int, 9>{});
+        step(zb, std::integral_constant<int, 10>{});
+        step(zb, std::integral_constant<int, 11>{});
+    }
+}
+
+// Projector term added to an H psi computed without it: hpsi += sum over the
+// spheres holding the point of gamma_A,i(p) (D_A,i P_A,i), one lane per
+// (state, point) of the points that lie in a sphere (eq. 6).  A lane serves
+// up to 4 blocks: the entry loads are shared and the 4 updates are
+// independent.
+template <typename T>
+__global__ void __launch_bounds__(256)
+nl_add_kernel(const int32_t *__restrict__ nl_pts, int64_t nnl, const int32_t *__restrict__ pt_ptr,
+              const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma, const T *__restrict__ dp,
+              T *__restrict__ hpsi, int64_t np, int B, int nat, int nblk) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nnl * B) return;
+    const int blk0 = 4 * blockIdx.y;
+    const int nb = min(4, nblk - blk0);
+    const int p = nl_pts[idx / B];
+    const int s = (int)(idx % B);
+    const int64_t dstride = (int64_t)nat * 4 * B;
+    const T *dpl = dp + blk0 * dstride + s;
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    for (int e = pt_ptr[p], e1 = pt_ptr[p + 1]; e < e1; ++e) {
+        const T *g = ent_gamma + 4 * (int64_t)e;
+        const T g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
+        const T *d = dpl + ent_atom[e] * 4 * B;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nb) {
+                const T *dk = d + k * dstride;
+                acc[k] += g0 * dk[0] + g1 * dk[B] + g2 * dk[2 * B] + g3 * dk[3 * B];
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < nb) {
+            T *y = hpsi + ((int64_t)(blk0 + k) * np + p) * B + s;
+            *y += acc[k];
+        }
+}
+
 // Non-local part 1 (eq. 6 integrals), stage 1: one work-group per (chunk of
 // <= 512 sphere entries of one atom, block).  Lanes: state s, row r; rows
 // stride through the chunk; FP64 sums are reduced over rows in a fixed tree.
@@ -442,6 +751,9 @@ nl_apply_kernel(const int32_t *__restrict__ pt_ptr, const int32_t *__restrict__ 
     *y = *y + acc;
 }
 
+#ifndef RS_MARCH
+#define RS_MARCH 1
+#endif
 #ifndef RS_NZF32
 #define RS_NZF32 2
 #endif
@@ -502,6 +814,51 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
     const T *dp = with_nl ? (const T *)nl->dp.p : nullptr;
     const int nat = with_nl ? nl->nat : 0;
     const T w0 = (T)w[0], w1 = (T)w[1], w2 = (T)w[2], w3 = (T)w[3];
+    // z-marching kernel (FP64): the full stencil when the block splits into
+    // state groups of RS_MARCH_RB = 128 bytes (B = 16, 32, 64)
+    if constexpr (R == 4 && RS_MARCH && (sizeof(T) == 8 || RS_MARCH_F32)) {
+        constexpr int SG = RS_MARCH_RB / (int)sizeof(T);
+        constexpr int PPT = sizeof(T) == 8 ? RS_MARCH_PPT64 : RS_MARCH_PPT32;
+        constexpr int NT = (64 / PPT) * SG;
+        const int64_t nsg = (int64_t)nblk * B / SG;
+        if (g->nmarch > 0 && B % SG == 0 && g->nmarch * nsg < (1ll << 30)) {
+            for (int pass = 0; pass < 2; ++pass) {
+                const bool full = pass == 0;
+                const int64_t n = full ? g->nmarch_full : g->nmarch - g->nmarch_full;
+                if (n == 0) continue;
+                const MarchChunk *mc = g->march_chunk.as<MarchChunk>() + (full ? 0 : g->nmarch_full);
+                const int nwg_pad = (int)((n * nsg + 7) & ~7ll);
+                dim3 grid(nwg_pad);
+#define RS_MARCH_LAUNCH(BB)                                                                          \
+    case BB:                                                                                         \
+        if constexpr (BB % SG == 0) {                                                                \
+            if (full)                                                                                \
+                hipLaunchKernelGGL((hpsi_march_kernel<T, BB, SG, PPT, true>), grid, dim3(NT), 0, st, mc, \
+                                   g->march_tab.as<MarchBrick>(), (int)n, (int)nsg, nwg_pad, psi, hpsi, vloc, vconst, \
+                                   g->np, pre, w0, w1, w2, w3);                                      \
+            else                                                                                     \
+                hipLaunchKernelGGL((hpsi_march_kernel<T, BB, SG, PPT, false>), grid, dim3(NT), 0, st, mc, \
+                                   g->march_tab.as<MarchBrick>(), (int)n, (int)nsg, nwg_pad, psi, hpsi, vloc, vconst, \
+                                   g->np, pre, w0, w1, w2, w3);                                      \
+        }                                                                                            \
+        break;
+                switch (B) {
+                    RS_MARCH_LAUNCH(8) RS_MARCH_LAUNCH(16) RS_MARCH_LAUNCH(32) RS_MARCH_LAUNCH(64)
+                    default:
+                        return fail(RS_ENOTSUP, "stencil: no z-marching kernel for this block size");
+                }
+#undef RS_MARCH_LAUNCH
+                RS_HIP(hipGetLastError());
+            }
+            if (with_nl && nl->nnlpts > 0) {
+                dim3 gn((unsigned)((nl->nnlpts * B + 255) / 256), (nblk + 3) / 4);
+                hipLaunchKernelGGL((nl_add_kernel<T>), gn, dim3(256), 0, st, nl->nl_pts.as<int32_t>(), nl->nnlpts,
+                                   ptp, eat, egm, dp, hpsi, g->np, B, nat, nblk);
+                RS_HIP(hipGetLastError());
+            }
+            return RS_OK;
+        }
+    }
     // interior bricks: NZF planes per wave; surface bricks: NZS
     constexpr int NZF = sizeof(T) == 8 ? RS_NZF64 : RS_NZF32;
     constexpr int NZS = sizeof(T) == 8 ? 1 : 2;

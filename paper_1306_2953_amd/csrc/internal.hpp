@@ -71,6 +71,28 @@ struct BrickRec {
 };
 static_assert(sizeof(BrickRec) == 40, "BrickRec layout");
 
+// Work of the z-marching stencil kernel: tiles of 2 x 2 bricks in x-y, each
+// tile's column of bricks cut along z into chunks of a multiple of 3 and at
+// most kMarchCZ brick layers.  A chunk's table holds, for its layers bz0-1 ..
+// bz0+nz+1 (nz + 3 layers, the last one always absent), 12 positions per
+// layer: the four tile bricks (position bx + 2 by),
+// then the neighbours across the -x side (rows 0, 1), the +x side (rows 0,
+// 1), the -y side (columns 0, 1) and the +y side (columns 0, 1).  An absent
+// brick has mask 0; id is the brick's number where the chunk owns (writes)
+// it, -1 otherwise (neighbours, and periodic images of bricks owned by
+// another tile).
+constexpr int kMarchCZ = 9;
+struct MarchBrick {
+    uint64_t mask;
+    int32_t start;
+    int32_t id;
+};
+static_assert(sizeof(MarchBrick) == 16, "MarchBrick layout");
+struct MarchChunk {
+    int32_t tab;   // first MarchBrick of the chunk's table
+    int32_t nz;    // brick layers written
+};
+
 }  // namespace rs
 
 struct rs_grid {
@@ -97,6 +119,11 @@ struct rs_grid {
     rs::DevBuf exec;         // int32[nbricks]: fast bricks, then the others,
                              // each list in Morton (Z-curve) order
     int64_t nfast = 0;
+    // z-marching work: chunks whose 12 x (nz + 2) table entries are all full
+    // bricks (and whose tile bricks are owned) first, then the others
+    rs::DevBuf march_chunk;  // MarchChunk[nmarch]
+    rs::DevBuf march_tab;    // MarchBrick[...]
+    int64_t nmarch = 0, nmarch_full = 0;
     int64_t lattice_index(int64_t i, int64_t j, int64_t k) const {
         return ((k - lo[2]) * L[1] + (j - lo[1])) * L[0] + (i - lo[0]);
     }
@@ -124,6 +151,8 @@ struct rs_nl {
     rs::DevBuf ent_atom;                                        // int32 [nent]
     rs::DevBuf ent_gamma64, ent_gamma32;                        // [nent][4]
     rs::DevBuf brick_nl;                                        // int32 [nbricks]
+    rs::DevBuf nl_pts;                                          // int32 [nnlpts]
+    int64_t nnlpts = 0;
     // scratch
     rs::DevBuf partial;   // double [max_states][nchunks][4]
     rs::DevBuf dp;        // dtype  [max_states][nat][4]  (D * projection)

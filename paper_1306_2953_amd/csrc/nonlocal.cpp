@@ -153,6 +153,12 @@ extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *p
             brick_nl[b] = cnt[r.start + n] > cnt[r.start];
         }
 
+    // the points that lie in at least one sphere, ascending
+    std::vector<int32_t> nl_pts;
+    for (int64_t p = 0; p < g->np; ++p)
+        if (cnt[p + 1] > cnt[p]) nl_pts.push_back((int32_t)p);
+    nl->nnlpts = (int64_t)nl_pts.size();
+
     std::vector<int32_t> sph32(nnz);
     for (int64_t e = 0; e < nnz; ++e) sph32[e] = (int32_t)nl->sph_idx[e];
     std::vector<float> g32(nl->gamma.begin(), nl->gamma.end());
@@ -177,6 +183,7 @@ extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *p
     if (!st) st = nl->ent_gamma64.upload(ent_g);
     if (!st) st = nl->ent_gamma32.upload(eg32);
     if (!st) st = nl->brick_nl.upload(brick_nl);
+    if (!st) st = nl->nl_pts.upload(nl_pts);
     if (!st) st = nl->partial.alloc(sizeof(double) * 4 * (size_t)max_states * std::max(nl->nchunks, 1));
     if (!st) st = nl->dp.alloc(sizeof(double) * 4 * (size_t)max_states * std::max(nat, 1));
     if (st) { delete nl; return st; }
