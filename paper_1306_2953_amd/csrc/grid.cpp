@@ -220,10 +220,9 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
         g->nfast = 0;
         for (int64_t b = 0; b < nbricks; ++b) g->nfast += (g->bricks_host[b].flags & kBrickFast) != 0;
         // z-marching chunks: tiles of 2 x 2 bricks; each tile's occupied z
-        // range cut at a global grid of kMarchCZ-layer bands (chunk ends at
-        // multiples of 3 layers, the kernel's unrolled step of 12 planes), so
-        // that the chunks of neighbouring tiles cover the same layers and,
-        // run together, share their x-y neighbour rows in L2.  Order: band,
+        // range cut at a global grid of kMarchCZ-layer bands, so that the
+        // chunks of neighbouring tiles cover the same layers and, run
+        // together, share their x-y neighbour rows in L2.  Order: band,
         // then the tiles along a 2-D Morton curve.  Table layers: bz0-1 ..
         // bz0+nz, then one absent layer (the kernel's last prefetches read it).
         const bool per = d->kind == RS_GRID_PERIODIC;
@@ -233,7 +232,7 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
         const int64_t ntx = (nbx + 1) / 2, nty = (nby + 1) / 2;
         static const int pdx[12] = {0, 1, 0, 1, -1, -1, 2, 2, 0, 1, 0, 1};
         static const int pdy[12] = {0, 0, 1, 1, 0, 1, 0, 1, -1, -1, 2, 2};
-        static_assert(kMarchCZ % 3 == 0, "bands are whole groups of 3 layers");
+
         for (int64_t ty = 0; ty < nty; ++ty)
             for (int64_t tx = 0; tx < ntx; ++tx) {
                 int64_t zmin = nbz, zmax = -1;
@@ -246,10 +245,9 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
                         }
                     }
                 if (zmax < 0) continue;
-                const int64_t lo3 = zmin / 3 * 3, hi3 = (zmax / 3 + 1) * 3;   // [lo3, hi3): whole triples
-                for (int64_t band = lo3 / kMarchCZ; band * kMarchCZ < hi3; ++band) {
-                    const int64_t bz0 = std::max(lo3, band * (int64_t)kMarchCZ);
-                    const int nz = (int)(std::min(hi3, (band + 1) * (int64_t)kMarchCZ) - bz0);
+                for (int64_t band = zmin / kMarchCZ; band * kMarchCZ <= zmax; ++band) {
+                    const int64_t bz0 = std::max(zmin, band * (int64_t)kMarchCZ);
+                    const int nz = (int)(std::min(zmax + 1, (band + 1) * (int64_t)kMarchCZ) - bz0);
                     MarchChunk mc{(int32_t)mtab.size(), nz};
                     bool full = true;
                     for (int l = 0; l < nz + 3; ++l) {

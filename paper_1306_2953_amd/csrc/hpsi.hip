@@ -376,8 +376,9 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
 // each plane's 128 x-y neighbour points, which the chunks of neighbouring
 // tiles in the same band (run at the same time on the same XCD) have just
 // brought into L2.  The step is unrolled over the 12 slots of the register
-// window (chunks are whole groups of 12 planes), so every ring index is a
-// compile-time constant and no load sits under a branch.
+// window, so every ring index is a compile-time constant and no load sits
+// under a branch; a chunk's last 4 or 8 planes run the first steps of the
+// same body.
 constexpr int kMW = 12;   // register window planes
 
 // Measured choices for the z-marching kernel: 128-byte state groups (64:
@@ -608,7 +609,8 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
                 bstore<T>(acc[k], rh, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), loff, ROWB));
         }
     };
-    for (int zb = 4; zb < zend; zb += kMW) {
+    int zb = 4;
+    for (; zb + kMW <= zend; zb += kMW) {
         step(zb, std::integral_constant<int, 0>{});
         step(zb, std::integral_constant<int, 1>{});
         step(zb, std::integral_constant<int, 2>{});
@@ -621,6 +623,19 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
         step(zb, std::integral_constant<int, 9>{});
         step(zb, std::integral_constant<int, 10>{});
         step(zb, std::integral_constant<int, 11>{});
+    }
+    // a last group of 4 or 8 planes: the first steps of the same body
+    if (zb < zend) {
+        step(zb, std::integral_constant<int, 0>{});
+        step(zb, std::integral_constant<int, 1>{});
+        step(zb, std::integral_constant<int, 2>{});
+        step(zb, std::integral_constant<int, 3>{});
+        if (zb + 4 < zend) {
+            step(zb, std::integral_constant<int, 4>{});
+            step(zb, std::integral_constant<int, 5>{});
+            step(zb, std::integral_constant<int, 6>{});
+            step(zb, std::integral_constant<int, 7>{});
+        }
     }
 }
 

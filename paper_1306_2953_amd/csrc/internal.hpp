@@ -72,8 +72,8 @@ struct BrickRec {
 static_assert(sizeof(BrickRec) == 40, "BrickRec layout");
 
 // Work of the z-marching stencil kernel: tiles of 2 x 2 bricks in x-y, each
-// tile's column of bricks cut along z into chunks of a multiple of 3 and at
-// most kMarchCZ brick layers.  A chunk's table holds, for its layers bz0-1 ..
+// tile's column of bricks cut along z into chunks of at most kMarchCZ brick
+// layers.  A chunk's table holds, for its layers bz0-1 ..
 // bz0+nz+1 (nz + 3 layers, the last one always absent), 12 positions per
 // layer: the four tile bricks (position bx + 2 by),
 // then the neighbours across the -x side (rows 0, 1), the +x side (rows 0,
