@@ -283,6 +283,172 @@ rotate_f64_lds_kernel(double *__restrict__ psi, const double *__restrict__ Xm, i
         }
 }
 
+// The same rotation with row-contiguous loads of psi (B a multiple of 16):
+// in each block of 16 states, lane group j = lane / 16 of a wave holds
+// states 4j .. 4j+3 of its point (one 32-byte load), so a wave reads 16
+// points x 128 contiguous bytes; MFMA step i of the block takes state
+// 4j + i from every group and the X rows in the same order, which sums the
+// same 16 products.  Two register buffers alternate so that the next
+// block's loads are in flight while the current one is multiplied.
+#ifndef RS_ROT_VEC
+#define RS_ROT_VEC 1
+#endif
+#ifndef RS_ROT_MT
+#define RS_ROT_MT 2          // 16-point row blocks per wave in the persistent rotation
+#endif
+template <int MT, int MAXC>
+__global__ void __launch_bounds__(512)
+rotate_f64_vec_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N,
+                      int ncb, const int *__restrict__ skip) {
+    extern __shared__ double xs[];              // [KR][ncb * 16 + 4]
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane >> 4, pl = lane & 15;
+    const int ld = ncb * 16 + 4;
+    const int64_t pw = ((int64_t)blockIdx.x * 8 + wave) * 16 * MT;
+    d4 acc[MT][MAXC];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) acc[m][c] = d4{0, 0, 0, 0};
+    auto load_a = [&](int k0, d4 (&a)[MT]) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int64_t pa = pw + m * 16 + pl;
+            a[m] = pa < np ? *(const d4 *)(psi + bidx(np, B, pa, k0 + 4 * j)) : d4{0, 0, 0, 0};
+        }
+    };
+    auto mma = [&](const d4 (&a)[MT], int k16) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = k16 + 4 * j + i;
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                if (c < ncb) {
+                    const double b = xs[r * ld + c * 16 + pl];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m][i], b, acc[m][c], 0, 0, 0);
+                }
+            }
+        }
+    };
+    static_assert(KR == 32, "two 16-state blocks per staged slice of X");
+    d4 a0[MT], a1[MT];
+    load_a(0, a0);
+    for (int kc = 0; kc < N; kc += KR) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < KR * ncb * 16; e += 512) {
+            const int r = e / (ncb * 16), col = e % (ncb * 16), k = kc + r;
+            xs[r * ld + col] = (k < N && col < N) ? Xm[(int64_t)k * N + col] : 0.0;
+        }
+        __syncthreads();
+        if (kc + 16 < N) load_a(kc + 16, a1);
+        mma(a0, 0);
+        if (kc + 32 < N) load_a(kc + 32, a0);
+        if (kc + 16 < N) mma(a1, 16);
+    }
+    // every read of this work-group's points is done before the first store
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            if (c < ncb) {
+                const int col = c * 16 + pl;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t p = pw + m * 16 + 4 * r + j;
+                    if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[m][c][r];
+                }
+            }
+        }
+}
+
+// Persistent form for N <= 128 (the padded X, N16 x (N16 + 4) doubles, fits
+// in LDS): one work-group per CU stages X once and walks point tiles of
+// 8 * 16 * MT points (tile = blockIdx.x + t * gridDim.x); the A loads of
+// the next 16-state block, across tile ends too, are in flight while the
+// current block is multiplied.  Each wave reads all N states of its own
+// points before it writes them, so the in-place update needs no barrier.
+constexpr int kRotXLds = 128 * (128 + 4) * 8;
+template <int MT>
+__global__ void __launch_bounds__(512)
+rotate_f64_px_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N, int ncb,
+                     int64_t ntiles, const int *__restrict__ skip) {
+    constexpr int MAXC = 8;
+    extern __shared__ double xs[];              // [N16][ncb * 16 + 4]
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane >> 4, pl = lane & 15;
+    const int ld = ncb * 16 + 4;
+    for (int e = threadIdx.x; e < ncb * 16 * ncb * 16; e += 512) {
+        const int r = e / (ncb * 16), col = e % (ncb * 16);
+        xs[r * ld + col] = (r < N && col < N) ? Xm[(int64_t)r * N + col] : 0.0;
+    }
+    __syncthreads();
+    const int nkb = N / 16;                     // 16-state blocks (N is a multiple of B >= 16)
+    auto load_a = [&](int64_t tile, int kb, d4 (&a)[MT]) {
+        const int64_t pw = (tile * 8 + wave) * 16 * MT;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int64_t pa = pw + m * 16 + pl;
+            a[m] = pa < np ? *(const d4 *)(psi + bidx(np, B, pa, 16 * kb + 4 * j)) : d4{0, 0, 0, 0};
+        }
+    };
+    d4 acc[MT][MAXC];
+    auto mma = [&](const d4 (&a)[MT], int kb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * kb + 4 * j + i;
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                if (c < ncb) {
+                    const double b = xs[r * ld + c * 16 + pl];
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+                        acc[m][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m][i], b, acc[m][c], 0, 0, 0);
+                }
+            }
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    d4 a0[MT], a1[MT];
+    load_a(tile, 0, a0);
+    while (true) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) acc[m][c] = d4{0, 0, 0, 0};
+        const int64_t next = tile + gridDim.x;
+        // blocks in pairs: a0 holds block kb, a1 block kb + 1
+        for (int kb = 0; kb < nkb; kb += 2) {
+            if (kb + 1 < nkb) load_a(tile, kb + 1, a1);
+            mma(a0, kb);
+            if (kb + 2 < nkb) load_a(tile, kb + 2, a0);
+            else if (next < ntiles) load_a(next, 0, a0);
+            if (kb + 1 < nkb) mma(a1, kb + 1);
+        }
+        const int64_t pw = (tile * 8 + wave) * 16 * MT;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                if (c < ncb) {
+                    const int col = c * 16 + pl;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t p = pw + m * 16 + 4 * r + j;
+                        if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[m][c][r];
+                    }
+                }
+            }
+        if (next >= ntiles) break;
+        tile = next;
+    }
+}
+
 // ------------------------------------------------------- rotation BF16x3
 // FP32 psi and the FP64 matrix X (transposed: xt0/1/2 [c][n]) are both split
 // in three bfloat16 terms, a = a0 + a1 + a2, x = x0 + x1 + x2, and the six
@@ -769,7 +935,29 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
     const int ncb = N16 / 16;
     if (dtype == RS_F64) {
         const size_t lds = (size_t)KR * (ncb * 16 + 4) * sizeof(double);
-        if (ncb <= 8) {
+        if (RS_ROT_VEC && B % 16 == 0 && ncb <= 8) {
+            // X resident in LDS, one persistent work-group per CU
+            if (!w.rot_lds_set) {
+                RS_HIP(hipFuncSetAttribute((const void *)rotate_f64_px_kernel<RS_ROT_MT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kRotXLds));
+                int dev = 0;
+                RS_HIP(hipGetDevice(&dev));
+                RS_HIP(hipDeviceGetAttribute(&w.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+                w.rot_lds_set = true;
+            }
+            const int64_t ntiles = (np + 128 * RS_ROT_MT - 1) / (128 * RS_ROT_MT);
+            const size_t xl = (size_t)N16 * (N16 + 4) * sizeof(double);
+            const unsigned grid = (unsigned)std::min<int64_t>(ntiles, std::max(w.ncu, 1));
+            hipLaunchKernelGGL((rotate_f64_px_kernel<RS_ROT_MT>), dim3(grid), dim3(512), xl, st, (double *)psi, Xm, np,
+                               B, N, ncb, ntiles, skip);
+        } else if (RS_ROT_VEC && B % 16 == 0) {
+            if (ncb <= 8)
+                hipLaunchKernelGGL((rotate_f64_vec_kernel<2, 8>), dim3((unsigned)((np + 255) / 256)), dim3(512), lds,
+                                   st, (double *)psi, Xm, np, B, N, ncb, skip);
+            else
+                hipLaunchKernelGGL((rotate_f64_vec_kernel<1, MAXC64>), dim3((unsigned)((np + 127) / 128)), dim3(512),
+                                   lds, st, (double *)psi, Xm, np, B, N, ncb, skip);
+        } else if (ncb <= 8) {
             const unsigned g2 = (unsigned)((np + 255) / 256);
             hipLaunchKernelGGL((rotate_f64_lds_kernel<2, 8>), dim3(g2), dim3(512), lds, st, (double *)psi, Xm, np, B, N,
                                ncb, skip);
