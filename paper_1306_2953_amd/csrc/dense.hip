@@ -49,11 +49,15 @@ __device__ __forceinline__ int64_t bidx(int64_t np, int B, int64_t p, int j) {
 // MFMA A and B fragments of a TN product both read 16 consecutive states of
 // one point, so LDS reads are conflict-free.
 constexpr int KC64 = 16;
+
 constexpr size_t kJacobiLds = 136 * 1024;   // dynamic LDS for the Jacobi matrix (N <= 130)
 constexpr int kMaxSweeps = 30;             // Jacobi sweep cap (rotation record size)
 constexpr int MAXB = 16;    // 16x16 blocks per wave
 
-template <bool SYRK>
+// NBW > 0: every wave owns exactly NBW blocks (b1 - b0 == 4 * NBW), and the
+// MFMAs run k outer, blocks inner, so consecutive ones feed independent
+// accumulators; NBW == 0: any share, one block's k steps at a time.
+template <bool SYRK, int NBW>
 __global__ void __launch_bounds__(256)
 gram_f64_kernel(const double *__restrict__ X, const double *__restrict__ Y, int64_t np, int B, int N,
                 int N16, int CP, const int2 *__restrict__ blocks, int nblocks, int bps,
@@ -69,6 +73,14 @@ gram_f64_kernel(const double *__restrict__ X, const double *__restrict__ Y, int6
     d4 acc[MAXB];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) acc[i] = d4{0, 0, 0, 0};
+    constexpr int NB = NBW > 0 ? NBW : 1;
+    int bx[NB], by[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int2 blk = NBW > 0 ? blocks[b0 + wave + 4 * i] : int2{0, 0};
+        bx[i] = blk.x;
+        by[i] = blk.y;
+    }
     for (int64_t p0 = p_beg; p0 < p_end; p0 += KC64) {
         for (int e = tid; e < KC64 * N16; e += 256) {
             const int p = e / N16, j = e % N16;
@@ -77,17 +89,30 @@ gram_f64_kernel(const double *__restrict__ X, const double *__restrict__ Y, int6
             if constexpr (!SYRK) ty[e] = ok ? Y[bidx(np, B, p0 + p, j)] : 0.0;
         }
         __syncthreads();
+        if constexpr (NBW > 0) {
 #pragma unroll
-        for (int i = 0; i < MAXB; ++i) {
-            const int bb = b0 + wave + 4 * i;
-            if (bb < b1) {
-                const int2 blk = blocks[bb];
+            for (int kk = 0; kk < KC64 / 4; ++kk) {
+                const int p = kk * 4 + lane / 16;
 #pragma unroll
-                for (int kk = 0; kk < KC64 / 4; ++kk) {
-                    const int p = kk * 4 + lane / 16;
-                    const double a = tx[p * N16 + blk.x * 16 + lane % 16];
-                    const double b = ty[p * N16 + blk.y * 16 + lane % 16];
+                for (int i = 0; i < NBW; ++i) {
+                    const double a = tx[p * N16 + bx[i] * 16 + lane % 16];
+                    const double b = ty[p * N16 + by[i] * 16 + lane % 16];
                     acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i) {
+                const int bb = b0 + wave + 4 * i;
+                if (bb < b1) {
+                    const int2 blk = blocks[bb];
+#pragma unroll
+                    for (int kk = 0; kk < KC64 / 4; ++kk) {
+                        const int p = kk * 4 + lane / 16;
+                        const double a = tx[p * N16 + blk.x * 16 + lane % 16];
+                        const double b = ty[p * N16 + blk.y * 16 + lane % 16];
+                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -371,17 +396,18 @@ rotate_f64_vec_kernel(double *__restrict__ psi, const double *__restrict__ Xm, i
 // the next 16-state block, across tile ends too, are in flight while the
 // current block is multiplied.  Each wave reads all N states of its own
 // points before it writes them, so the in-place update needs no barrier.
-constexpr int kRotXLds = 128 * (128 + 4) * 8;
+constexpr int kRotPad = 4;    // doubles of padding per LDS row of X
+constexpr int kRotXLds = 128 * (128 + kRotPad) * 8;
 template <int MT>
 __global__ void __launch_bounds__(512)
 rotate_f64_px_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N, int ncb,
                      int64_t ntiles, const int *__restrict__ skip) {
     constexpr int MAXC = 8;
-    extern __shared__ double xs[];              // [N16][ncb * 16 + 4]
+    extern __shared__ double xs[];              // [N16][ncb * 16 + kRotPad]
     if (skip && *skip) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = lane >> 4, pl = lane & 15;
-    const int ld = ncb * 16 + 4;
+    const int ld = ncb * 16 + kRotPad;
     for (int e = threadIdx.x; e < ncb * 16 * ncb * 16; e += 512) {
         const int r = e / (ncb * 16), col = e % (ncb * 16);
         xs[r * ld + col] = (r < N && col < N) ? Xm[(int64_t)r * N + col] : 0.0;
@@ -903,12 +929,21 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
     dim3 grid(nchunks, nsplit);
     if (dtype == RS_F64) {
         const size_t lds = (syrk ? 1 : 2) * (size_t)KC64 * N16 * sizeof(double);
-        if (syrk)
-            hipLaunchKernelGGL(gram_f64_kernel<true>, grid, dim3(256), lds, st, (const double *)X, (const double *)Y,
-                               np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>());
-        else
-            hipLaunchKernelGGL(gram_f64_kernel<false>, grid, dim3(256), lds, st, (const double *)X, (const double *)Y,
-                               np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>());
+        // exact per-wave share: every work-group holds bps = 4 * nbw blocks
+        const int nbw = (bps % 4 == 0 && nblocks % bps == 0) ? bps / 4 : 0;
+#define RS_GRAM64(S, NB)                                                                                  \
+    hipLaunchKernelGGL((gram_f64_kernel<S, NB>), grid, dim3(256), lds, st, (const double *)X, (const double *)Y, \
+                       np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>())
+        // (the interleaved form is faster at 9 blocks per wave, the symmetric
+        // product of 128 states; at 16 its 128 accumulators cost occupancy)
+        if (nbw == 9) {
+            if (syrk) RS_GRAM64(true, 9);
+            else RS_GRAM64(false, 9);
+        } else {
+            if (syrk) RS_GRAM64(true, 0);
+            else RS_GRAM64(false, 0);
+        }
+#undef RS_GRAM64
     } else if (bf) {
         const size_t lds = (syrk ? 2 : 4) * (size_t)N16 * LDSROW * sizeof(unsigned short);
         if (syrk)
@@ -946,7 +981,7 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
                 w.rot_lds_set = true;
             }
             const int64_t ntiles = (np + 128 * RS_ROT_MT - 1) / (128 * RS_ROT_MT);
-            const size_t xl = (size_t)N16 * (N16 + 4) * sizeof(double);
+            const size_t xl = (size_t)N16 * (N16 + kRotPad) * sizeof(double);
             const unsigned grid = (unsigned)std::min<int64_t>(ntiles, std::max(w.ncu, 1));
             hipLaunchKernelGGL((rotate_f64_px_kernel<RS_ROT_MT>), dim3(grid), dim3(512), xl, st, (double *)psi, Xm, np,
                                B, N, ncb, ntiles, skip);
