@@ -141,7 +141,11 @@ gram_f64_kernel(const double *__restrict__ X, const double *__restrict__ Y, int6
 constexpr int KCB = 32;
 constexpr int LDSROW = KCB + 8;   // bf16 elements per state row (padding)
 
-template <bool SYRK>
+// VEC (B a multiple of 4): a thread stages 4 consecutive points x 4
+// consecutive states, read as four 16-byte loads (8 threads cover 128
+// contiguous bytes of a point row) and written as one 8-byte LDS store per
+// state and term (4 points of one state row).
+template <bool SYRK, bool VEC>
 __global__ void __launch_bounds__(256)
 gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_t np, int B, int N,
                    int N16, int CP, const int2 *__restrict__ blocks, int nblocks, int bps,
@@ -158,19 +162,51 @@ gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int
     d4 acc[MAXB];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) acc[i] = d4{0, 0, 0, 0};
+    // split v into hi + lo bfloat16 for 4 points of one state, packed
+    auto put4 = [&](const f4 (&v)[4], int s, unsigned short *hi, unsigned short *lo, int off) {
+        unsigned short h[4], l[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            h[t] = bf16_rne(v[t][s]);
+            l[t] = bf16_rne(v[t][s] - bf16_to_f(h[t]));
+        }
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        *(u2 *)(hi + off) = u2{(unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16)};
+        *(u2 *)(lo + off) = u2{(unsigned)l[0] | ((unsigned)l[1] << 16), (unsigned)l[2] | ((unsigned)l[3] << 16)};
+    };
     for (int64_t p0 = p_beg; p0 < p_end; p0 += KCB) {
-        for (int e = tid; e < KCB * N16; e += 256) {
-            const int p = e / N16, j = e % N16;
-            const bool ok = p0 + p < p_end && j < N;
-            const float v = ok ? X[bidx(np, B, p0 + p, j)] : 0.0f;
-            const unsigned short h = bf16_rne(v);
-            xh[j * LDSROW + p] = h;
-            xl[j * LDSROW + p] = bf16_rne(v - bf16_to_f(h));
-            if constexpr (!SYRK) {
-                const float w = ok ? Y[bidx(np, B, p0 + p, j)] : 0.0f;
-                const unsigned short g = bf16_rne(w);
-                yh[j * LDSROW + p] = g;
-                yl[j * LDSROW + p] = bf16_rne(w - bf16_to_f(g));
+        if constexpr (VEC) {
+            for (int q = tid; q < 2 * N16; q += 256) {
+                const int pq = q & 7, j0 = 4 * (q >> 3);
+                f4 v[4], w[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t p = p0 + 4 * pq + t;
+                    const bool ok = p < p_end && j0 < N;
+                    v[t] = ok ? *(const f4 *)(X + bidx(np, B, p, j0)) : f4{0, 0, 0, 0};
+                    if constexpr (!SYRK) w[t] = ok ? *(const f4 *)(Y + bidx(np, B, p, j0)) : f4{0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int off = (j0 + s) * LDSROW + 4 * pq;
+                    put4(v, s, xh, xl, off);
+                    if constexpr (!SYRK) put4(w, s, yh, yl, off);
+                }
+            }
+        } else {
+            for (int e = tid; e < KCB * N16; e += 256) {
+                const int p = e / N16, j = e % N16;
+                const bool ok = p0 + p < p_end && j < N;
+                const float v = ok ? X[bidx(np, B, p0 + p, j)] : 0.0f;
+                const unsigned short h = bf16_rne(v);
+                xh[j * LDSROW + p] = h;
+                xl[j * LDSROW + p] = bf16_rne(v - bf16_to_f(h));
+                if constexpr (!SYRK) {
+                    const float w = ok ? Y[bidx(np, B, p0 + p, j)] : 0.0f;
+                    const unsigned short g = bf16_rne(w);
+                    yh[j * LDSROW + p] = g;
+                    yl[j * LDSROW + p] = bf16_rne(w - bf16_to_f(g));
+                }
             }
         }
         __syncthreads();
@@ -946,12 +982,17 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
 #undef RS_GRAM64
     } else if (bf) {
         const size_t lds = (syrk ? 2 : 4) * (size_t)N16 * LDSROW * sizeof(unsigned short);
-        if (syrk)
-            hipLaunchKernelGGL(gram_bf16x3_kernel<true>, grid, dim3(256), lds, st, (const float *)X, (const float *)Y,
-                               np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>());
-        else
-            hipLaunchKernelGGL(gram_bf16x3_kernel<false>, grid, dim3(256), lds, st, (const float *)X, (const float *)Y,
-                               np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>());
+#define RS_GRAMBF(S, V)                                                                                   \
+    hipLaunchKernelGGL((gram_bf16x3_kernel<S, V>), grid, dim3(256), lds, st, (const float *)X, (const float *)Y, \
+                       np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>())
+        if (B % 4 == 0) {
+            if (syrk) RS_GRAMBF(true, true);
+            else RS_GRAMBF(false, true);
+        } else {
+            if (syrk) RS_GRAMBF(true, false);
+            else RS_GRAMBF(false, false);
+        }
+#undef RS_GRAMBF
     } else {
         return fail(RS_ENOTSUP, "gram: FP32 data needs RS_PREC_BF16X3");
     }
