@@ -623,6 +623,123 @@ split_xt_kernel(const double *__restrict__ Xm, int N, int N16, int N32, unsigned
     xtl[idx] = bf16_rne((float)r2);
 }
 
+// Persistent BF16x3 rotation for N32 <= 128 and B a multiple of 8: one
+// work-group per CU holds the three X terms of every 32-row slice in LDS
+// ([slice][term][column][XLD]) and walks point tiles; a lane's 8 states of
+// one point are two 16-byte loads, and the next slice's (or tile's) loads
+// are in flight while the current slice is multiplied.  The splitting of
+// psi and the order of the six products are those of the kernel above.
+constexpr int kRotBfLds = 4 * 3 * 128 * XLD * 2;
+template <int MT>
+__global__ void __launch_bounds__(512)
+rotate_bf16x3_px_kernel(float *__restrict__ psi, const unsigned short *__restrict__ xth,
+                        const unsigned short *__restrict__ xtl, const unsigned short *__restrict__ xtm,
+                        int64_t np, int B, int N, int N32, int ncb, int64_t ntiles, const int *__restrict__ skip) {
+    constexpr int MAXC = 8;
+    extern __shared__ unsigned short xl[];
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ncol = ncb * 16, nsl = N32 / 32;
+    for (int e = threadIdx.x; e < nsl * 3 * ncol * 4; e += 512) {
+        const int q = e & 3, col = (e >> 2) % ncol, rest = (e >> 2) / ncol;
+        const int term = rest % 3, sl = rest / 3;
+        const unsigned short *src = term == 0 ? xth : (term == 1 ? xtm : xtl);
+        *(us8 *)(xl + ((sl * 3 + term) * ncol + col) * XLD + 8 * q) =
+            *(const us8 *)(src + (int64_t)col * N32 + sl * 32 + 8 * q);
+    }
+    __syncthreads();
+    auto load_a = [&](int64_t tile, int sl, f4 (&a)[MT][2]) {
+        const int64_t pw = (tile * 8 + wave) * 16 * MT;
+        const int kb = sl * 32 + 8 * (lane / 16);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int64_t pa = pw + m * 16 + lane % 16;
+            if (pa < np && kb < N) {
+                const float *src = psi + bidx(np, B, pa, kb);
+                a[m][0] = *(const f4 *)src;
+                a[m][1] = *(const f4 *)(src + 4);
+            } else {
+                a[m][0] = f4{0, 0, 0, 0};
+                a[m][1] = f4{0, 0, 0, 0};
+            }
+        }
+    };
+    f4 acc[MT][MAXC];
+    auto mma = [&](const f4 (&a)[MT][2], int sl) {
+        bf8 A0[MT], A1[MT], A2[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            us8 a0, a1, a2;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float v = a[m][t >> 2][t & 3];
+                const unsigned short h0 = bf16_rne(v);
+                const float r1 = v - bf16_to_f(h0);
+                const unsigned short h1 = bf16_rne(r1);
+                a0[t] = h0;
+                a1[t] = h1;
+                a2[t] = bf16_rne(r1 - bf16_to_f(h1));
+            }
+            A0[m] = __builtin_bit_cast(bf8, a0);
+            A1[m] = __builtin_bit_cast(bf8, a1);
+            A2[m] = __builtin_bit_cast(bf8, a2);
+        }
+        const unsigned short *xs = xl + sl * 3 * ncol * XLD;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            if (c < ncb) {
+                const int o = (c * 16 + lane % 16) * XLD + 8 * (lane / 16);
+                const bf8 X0 = __builtin_bit_cast(bf8, *(const us8 *)(xs + o));
+                const bf8 X1 = __builtin_bit_cast(bf8, *(const us8 *)(xs + ncol * XLD + o));
+                const bf8 X2 = __builtin_bit_cast(bf8, *(const us8 *)(xs + 2 * ncol * XLD + o));
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A2[m], X0, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[m], X1, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], X2, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1[m], X0, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], X1, acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], X0, acc[m][c], 0, 0, 0);
+                }
+            }
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    f4 a0[MT][2], a1[MT][2];
+    load_a(tile, 0, a0);
+    while (true) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) acc[m][c] = f4{0, 0, 0, 0};
+        const int64_t next = tile + gridDim.x;
+        for (int sl = 0; sl < nsl; sl += 2) {
+            if (sl + 1 < nsl) load_a(tile, sl + 1, a1);
+            mma(a0, sl);
+            if (sl + 2 < nsl) load_a(tile, sl + 2, a0);
+            else if (next < ntiles) load_a(next, 0, a0);
+            if (sl + 1 < nsl) mma(a1, sl + 1);
+        }
+        const int64_t pw = (tile * 8 + wave) * 16 * MT;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                if (c < ncb) {
+                    const int col = c * 16 + lane % 16;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t p = pw + m * 16 + 4 * (lane / 16) + r;
+                        if (p < np && col < N) psi[bidx(np, B, p, col)] = acc[m][c][r];
+                    }
+                }
+            }
+        if (next >= ntiles) break;
+        tile = next;
+    }
+}
+
 // ------------------------------------------------------------- Cholesky
 // S = U^T U, U upper with positive diagonal (right-looking, one work-group;
 // the working copy W lives in LDS when it fits, else in global memory).
@@ -1048,7 +1165,23 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
                            w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(), w.xtm.as<unsigned short>());
         RS_HIP(hipGetLastError());
         const size_t lds = (size_t)3 * ncb * 16 * XLD * sizeof(unsigned short);
-        if (ncb <= 8)
+        if (RS_ROT_VEC && B % 8 == 0 && ncb <= 8 && N32 <= 128) {
+            // all slices of X resident in LDS, one persistent work-group per CU
+            if (!w.rotbf_lds_set) {
+                RS_HIP(hipFuncSetAttribute((const void *)rotate_bf16x3_px_kernel<2>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kRotBfLds));
+                int dev = 0;
+                RS_HIP(hipGetDevice(&dev));
+                RS_HIP(hipDeviceGetAttribute(&w.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+                w.rotbf_lds_set = true;
+            }
+            const int64_t ntiles = (np + 255) / 256;
+            const size_t xlb = (size_t)(N32 / 32) * 3 * ncb * 16 * XLD * sizeof(unsigned short);
+            const unsigned grid = (unsigned)std::min<int64_t>(ntiles, std::max(w.ncu, 1));
+            hipLaunchKernelGGL((rotate_bf16x3_px_kernel<2>), dim3(grid), dim3(512), xlb, st, (float *)psi,
+                               w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(), w.xtm.as<unsigned short>(), np,
+                               B, N, N32, ncb, ntiles, skip);
+        } else if (ncb <= 8)
             hipLaunchKernelGGL((rotate_bf16x3_lds_kernel<2, 8>), dim3((unsigned)((np + 255) / 256)), dim3(512), lds,
                                st, (float *)psi, w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(),
                                w.xtm.as<unsigned short>(), np, B, N, N32, ncb, skip);

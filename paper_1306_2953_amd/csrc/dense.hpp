@@ -21,7 +21,7 @@ struct DenseWork {
     DevBuf sweeps;                     // int
     DevBuf diag;                       // double [N] Jacobi diagonal
     DevBuf rot;                        // double2 [30][M-1][M/2] Jacobi rotations
-    bool jacobi_lds_set = false, chol_lds_set = false, rot_lds_set = false;
+    bool jacobi_lds_set = false, chol_lds_set = false, rot_lds_set = false, rotbf_lds_set = false;
     int ncu = 0;                       // compute units of the device (persistent rotation)
 };
 
