@@ -248,20 +248,34 @@ gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int
     }
 }
 
-// Fixed-order FP64 sum of the chunk partials, one wave per output entry;
-// SYRK (mode 1) mirrors the upper blocks, mode 2 symmetrises (M + M^T)/2.
-// Output S [N][N] = dv * sum.
+// Two-pass fixed-order FP64 sum of the chunk partials.  Pass 1: thread
+// (entry e of the N16 x N16 partial, group g) sums chunks g*cpg .. in order
+// (consecutive threads read consecutive entries of one chunk); pass 2: one
+// thread per output entry sums the groups in order, mirrors (SYRK, mode 1)
+// or symmetrises (mode 2), and scales by dv.
+constexpr int kRedGroups = 16;
 __global__ void __launch_bounds__(256)
-gram_reduce_kernel(const double *__restrict__ partial, int nchunks, int N, int N16, int mode,
-                   double dv, double *__restrict__ S) {
-    const int lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+gram_reduce1_kernel(const double *__restrict__ partial, int nchunks, int cpg, int64_t ne,
+                    double *__restrict__ red) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int g = blockIdx.y;
+    if (e >= ne) return;
+    const int c0 = g * cpg, c1 = min(nchunks, c0 + cpg);
+    double sum = 0.0;
+    for (int c = c0; c < c1; ++c) sum += partial[(int64_t)c * ne + e];
+    red[(int64_t)g * ne + e] = sum;
+}
+__global__ void __launch_bounds__(256)
+gram_reduce2_kernel(const double *__restrict__ red, int ng, int N, int N16, int mode, double dv,
+                    double *__restrict__ S) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= N * N) return;
     const int i = idx / N, j = idx % N;
+    const int64_t ne = (int64_t)N16 * N16;
     auto sum = [&](int a, int b) {
-        double s = 0.0;
-        for (int c = lane; c < nchunks; c += 64) s += partial[((int64_t)c * N16 + a) * N16 + b];
-        return wave_sum(s);
+        double v = 0.0;
+        for (int g = 0; g < ng; ++g) v += red[g * ne + (int64_t)a * N16 + b];
+        return v;
     };
     double v;
     if (mode == 1) {
@@ -272,7 +286,7 @@ gram_reduce_kernel(const double *__restrict__ partial, int nchunks, int N, int N
     } else {
         v = sum(i, j);
     }
-    if (lane == 0) S[idx] = dv * v;
+    S[idx] = dv * v;
 }
 
 // --------------------------------------------------------- rotation FP64
@@ -1115,8 +1129,16 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
     }
     RS_HIP(hipGetLastError());
     const int rmode = syrk ? 1 : mode;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((N * N + 3) / 4), dim3(256), 0, st, w.partial.as<double>(),
-                       nchunks, N, N16, rmode, dv, S);
+    {
+        const int64_t ne = (int64_t)N16 * N16;
+        const int ng = std::min(kRedGroups, nchunks);
+        const int cpg = (nchunks + ng - 1) / ng;
+        hipLaunchKernelGGL(gram_reduce1_kernel, dim3((unsigned)((ne + 255) / 256), ng), dim3(256), 0, st,
+                           w.partial.as<double>(), nchunks, cpg, ne, w.red.as<double>());
+        RS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(gram_reduce2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, w.red.as<double>(), ng,
+                           N, N16, rmode, dv, S);
+    }
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -1255,6 +1277,7 @@ rs_status dense_work_init(DenseWork &w, int64_t np, int max_states) {
     rs_status s = RS_OK;
     const size_t nb16 = (size_t)(N16 / 16) * (N16 / 16);
     if (!s) s = w.partial.alloc((size_t)w.max_chunks * N16 * N16 * sizeof(double));
+    if (!s) s = w.red.alloc((size_t)kRedGroups * N16 * N16 * sizeof(double));
     if (!s) s = w.d_blocks_syrk.alloc(nb16 * sizeof(int2));
     if (!s) s = w.d_blocks_full.alloc(nb16 * sizeof(int2));
     if (!s) s = w.mwork.alloc((size_t)max_states * max_states * sizeof(double));

@@ -13,6 +13,7 @@ struct DenseWork {
     int max_states = 0;
     int max_chunks = 512;               // set by dense_work_init
     DevBuf partial;                    // double [max_chunks][N16][N16]
+    DevBuf red;                        // double [16][N16][N16] group sums of the partials
     std::vector<int2> blocks_syrk, blocks_full;
     int blocks_n = 0;
     DevBuf d_blocks_syrk, d_blocks_full;
