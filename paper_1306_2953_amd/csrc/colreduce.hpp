@@ -25,6 +25,8 @@ colreduce_kernel(Op op, int64_t np, int B, int nchunks, int N, double *__restric
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    // unrolled so that several points' loads are in flight per thread
+#pragma unroll 4
     for (int64_t p = p0 + r; p < p1; p += R) op((int64_t)blk * np * B + p * B + s, col, acc);
 #pragma unroll
     for (int k = 0; k < K; ++k) red[k][tid] = acc[k];

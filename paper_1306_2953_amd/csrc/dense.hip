@@ -889,7 +889,12 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
         if (stop) break;
         for (int r = 0; r < M - 1; ++r) {
             for (int k = tid; k < h; k += blockDim.x) {
-                auto pos = [&](int i) { return i == 0 ? 0 : ((i - 1 + r) % (M - 1)) + 1; };
+                auto pos = [&](int i) {
+                    if (i == 0) return 0;
+                    int x = i - 1 + r;               // < 2 (M - 1)
+                    if (x >= M - 1) x -= M - 1;
+                    return x + 1;
+                };
                 int p = pos(k), q = pos(M - 1 - k);
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;

@@ -130,10 +130,12 @@ template <typename T, int NIT> struct OpDiis {
 template <typename T>
 __global__ void __launch_bounds__(256)
 axpy1_kernel(const T *__restrict__ x, const T *__restrict__ d, T *y, const double *__restrict__ lam, int64_t np,
-             int B, int64_t total) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const int c = (int)(i / (np * B)) * B + (int)(i % B);
+             int B) {
+    // blockIdx.y: the block; B is a power of two
+    const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (il >= np * B) return;
+    const int64_t i = (int64_t)blockIdx.y * np * B + il;
+    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
     y[i] = (T)((double)x[i] + lam[c] * (double)d[i]);
 }
 
@@ -145,12 +147,14 @@ template <typename T> struct Hist {
 template <typename T, int NIT>
 __global__ void __launch_bounds__(256)
 combine_kernel(Hist<T> H, const double *__restrict__ eps, const double *__restrict__ coef, T *__restrict__ xb,
-               T *__restrict__ hb, T *__restrict__ rb, int64_t np, int B, int N, int64_t total) {
+               T *__restrict__ hb, T *__restrict__ rb, int64_t np, int B, int N) {
     const T *const *xs = H.x;
     const T *const *hs = H.h;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const int c = (int)(i / (np * B)) * B + (int)(i % B);
+    // blockIdx.y: the block; B is a power of two
+    const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (il >= np * B) return;
+    const int64_t i = (int64_t)blockIdx.y * np * B + il;
+    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
     const double xl = xs[NIT - 1][i], hl = hs[NIT - 1][i];
     const double rl = hl - eps[(NIT - 1) * N + c] * xl;
     double sx = coef[c * kMaxHist] * xl, sh = coef[c * kMaxHist] * hl, sr = coef[c * kMaxHist] * rl;
@@ -470,8 +474,7 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     const int64_t np = g->np;
     const int B = S->B, nblk = S->nblk, N = S->N, m = S->opts.m;
     const double dv = g->h * g->h * g->h;
-    const int64_t total = np * N;
-    const unsigned gm = (unsigned)((total + 255) / 256);
+    const dim3 gb((unsigned)((np * B + 255) / 256), nblk);   // per-block grid (y: the block)
     const unsigned gs = (unsigned)((N + 63) / 64);
     T *h0 = S->hh[0].as<T>();
     double *partial = S->partial.as<double>();
@@ -511,8 +514,8 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     hs[0] = h0;
     if (m == 1) {
         // the trial iterate is the newest: straight into psi (in place)
-        hipLaunchKernelGGL(axpy1_kernel<T>, dim3(gm), dim3(256), 0, st, psi, S->d.as<T>(), psi,
-                           S->lam.as<double>(), np, B, total);
+        hipLaunchKernelGGL(axpy1_kernel<T>, gb, dim3(256), 0, st, psi, S->d.as<T>(), psi,
+                           S->lam.as<double>(), np, B);
         RS_HIP(hipGetLastError());
         return RS_OK;
     }
@@ -545,11 +548,11 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
             hist.h[i] = hs[i];
         }
         if (n == 2)
-            hipLaunchKernelGGL((combine_kernel<T, 2>), dim3(gm), dim3(256), 0, st, hist, S->eps.as<double>(),
-                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, total);
+            hipLaunchKernelGGL((combine_kernel<T, 2>), gb, dim3(256), 0, st, hist, S->eps.as<double>(),
+                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N);
         else
-            hipLaunchKernelGGL((combine_kernel<T, 3>), dim3(gm), dim3(256), 0, st, hist, S->eps.as<double>(),
-                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, total);
+            hipLaunchKernelGGL((combine_kernel<T, 3>), gb, dim3(256), 0, st, hist, S->eps.as<double>(),
+                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N);
         RS_HIP(hipGetLastError());
         if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
         if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
@@ -560,8 +563,8 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
         } else {
             // the newest iterate goes straight into psi (frozen states: it
             // equals psi); its H psi is not needed
-            hipLaunchKernelGGL(axpy1_kernel<T>, dim3(gm), dim3(256), 0, st, xb, S->d.as<T>(), psi,
-                               S->lam.as<double>(), np, B, total);
+            hipLaunchKernelGGL(axpy1_kernel<T>, gb, dim3(256), 0, st, xb, S->d.as<T>(), psi,
+                               S->lam.as<double>(), np, B);
         }
         xs[n] = xb;
         hs[n] = hb;
