@@ -85,6 +85,26 @@ def test_hpsi_box_harmonic_and_periodic():
     assert _relerr(got, H.apply(psi)) < 1e-12
 
 
+@pytest.mark.parametrize("kind,n,nat", [("periodic", 4, 0), ("periodic", 12, 0), ("periodic", 20, 2),
+                                         ("box", 13, 0)])
+def test_hpsi_fp64_march_lattice_edges(kind, n, nat):
+    """FP64 blocks of 16 and 32 states run the z-marching kernel.  Periodic
+    edges of 1, 3 and 5 bricks leave the last 2 x 2 tile half outside the
+    lattice (its second column wraps onto bricks another tile writes: they
+    are read as neighbours, never written); the Dirichlet box has partial
+    bricks on every face."""
+    if kind == "periodic":
+        w = synthetic.make_config(4, n=n, nat=nat, rc=1.5)
+    else:
+        w = synthetic.make_config(1, n=n)
+    og, H, g, nl = _system(w)
+    psi = _states(w, 64, og.np, np.float64)
+    want = H.apply(psi)
+    for B in (16, 32):
+        got = _gpu_hpsi(g, nl, H.vloc, psi, B, np.float64)
+        assert _relerr(got, want) < 1e-12, (kind, n, B)
+
+
 def test_overlapping_spheres_no_race():
     w = synthetic.make_config(2, radius=2.4, nat=8, atom_radius=0.8, rc=1.5)
     og, H, g, nl = _system(w)
