@@ -45,6 +45,11 @@ def test_overlap_fp64(small, nblk, B):
     want = linalg.overlap(x, og.dv)
     assert np.max(np.abs(S - want)) <= 1e-12 * np.max(np.abs(want))
     assert np.array_equal(S, S.T)
+    # one tensor for both operands: the symmetric (upper blocks) product
+    tx = _blk(x, B)
+    Ss = ctx.overlap(tx, tx).cpu().numpy()
+    assert np.max(np.abs(Ss - want)) <= 1e-12 * np.max(np.abs(want))
+    assert np.array_equal(Ss, Ss.T)
     M = ctx.overlap(_blk(x, B), _blk(y, B)).cpu().numpy()
     want = og.dv * x @ y.T
     assert np.max(np.abs(M - want)) <= 1e-12 * np.max(np.abs(want))
@@ -58,8 +63,9 @@ def test_overlap_bf16x3_error_bound(small, nblk, B):
     x = rng.uniform(-1, 1, (nblk * B, og.np)).astype(np.float32)
     y = rng.uniform(-1, 1, (nblk * B, og.np)).astype(np.float32)
     x64, y64 = x.astype(np.float64), y.astype(np.float64)
-    for a, b in ((x, x), (x, y)):
-        got = ctx.overlap(_blk(a, B), _blk(b, B)).cpu().numpy()
+    for a, b, same in ((x, x, True), (x, x, False), (x, y, False)):
+        ta = _blk(a, B)
+        got = ctx.overlap(ta, ta if same else _blk(b, B)).cpu().numpy()
         want = og.dv * a.astype(np.float64) @ b.astype(np.float64).T
         bound = 2.0 ** -15 * og.dv * np.abs(a.astype(np.float64)) @ np.abs(b.astype(np.float64)).T
         assert np.all(np.abs(got - want) <= bound)
@@ -101,8 +107,12 @@ def test_eigh_jacobi(small, N):
 
 
 @pytest.mark.parametrize("dtype,nblk,B", [(np.float64, 3, 32), (np.float64, 5, 8), (np.float32, 4, 32),
-                                          (np.float32, 2, 8)])
+                                          (np.float32, 2, 8), (np.float64, 5, 32), (np.float64, 3, 16),
+                                          (np.float32, 5, 32), (np.float32, 3, 16)])
 def test_rotate(small, dtype, nblk, B):
+    """N <= 128 with B a multiple of 16 (FP64) or 8 (FP32) runs the
+    persistent kernels (48 states: an odd count of 16-state blocks, a padded
+    last 32-row slice); N = 160 the tiled ones."""
     w, og, H, g, ctx = small
     N = nblk * B
     rng = np.random.default_rng(N)
