@@ -693,6 +693,8 @@ nl_partial_kernel(const int32_t *__restrict__ chunk_beg, const int32_t *__restri
     const int e0 = chunk_beg[chunk], e1 = chunk_end[chunk];
     psi += blk * blk_stride;
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    // unrolled so that several entries' gathers are in flight per thread
+#pragma unroll 4
     for (int e = e0 + r; e < e1; e += R) {
         const double x = (double)psi[sph_idx[e] * B + s];
         const T *g = gamma + 4 * (int64_t)e;
