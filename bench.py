@@ -14,7 +14,7 @@ states, with inputs resident in HBM.  Prints one JSON line:
              FP64 filter solve and the FP32 split-precision solve,
   cpu_baseline = the FP64 C/OpenMP oracle on the host cores (bounded sample).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3|5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--no-eig] [--no-cpu] [--no-fp32]
 """
 from __future__ import annotations
@@ -34,6 +34,9 @@ sys.path.insert(0, ROOT)
 import synthetic  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# the workload the headline metric is quoted on, and the FP32 ones
+PRIMARY = "sphere_r12_h0.2"
+FP32_WORKLOADS = ("sphere_r12_h0.2_fp32", "periodic96_h0.25", "sphere_r18_h0.18_cage60")
 
 
 def log(msg):
@@ -357,7 +360,7 @@ def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
 def eigensolve_compare(max_steps=600):
     """Plain FP64 filter solve on the 128-state sphere (its converged end is
     the reference) against the FP32 split-precision solve of the same system."""
-    w2, w3 = synthetic.CONFIGS[2], synthetic.CONFIGS[3]
+    w2, w3 = synthetic.WORKLOADS["sphere_r12_h0.2"], synthetic.WORKLOADS["sphere_r12_h0.2_fp32"]
     log("eigensolve: FP64 reference / plain run")
     r64 = eigensolve_run(w2, "f64", w2.block, max_steps, 1e-6)
     ref = r64["eig"]
@@ -386,7 +389,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--workload", default=PRIMARY, choices=sorted(synthetic.WORKLOADS))
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -405,39 +408,40 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    w = synthetic.CONFIGS[a.config]
+    w = synthetic.WORKLOADS[a.workload]
     B = a.block or w.block
+    dtype = "f32" if w.name in FP32_WORKLOADS else "f64"
+    primary = w.name == PRIMARY
     if a.profile_eig:
-        for cfg, dt in ((2, "f64"), (3, "f32")):
-            r = eigensolve_run(synthetic.CONFIGS[cfg], dt, synthetic.CONFIGS[cfg].block, a.profile_eig, 0.0,
-                               log_every=1)
-            log(f"{synthetic.CONFIGS[cfg].name} {dt}: step times {np.diff([0.0] + r['times'])}")
+        for name, dt in ((PRIMARY, "f64"), (PRIMARY + "_fp32", "f32")):
+            wk = synthetic.WORKLOADS[name]
+            r = eigensolve_run(wk, dt, wk.block, a.profile_eig, 0.0, log_every=1)
+            log(f"{wk.name} {dt}: step times {np.diff([0.0] + r['times'])}")
         return
     if a.traffic_record:
-        traffic_record(w, "f32" if a.config in (3, 4, 5) else "f64", *a.traffic_record)
+        traffic_record(w, dtype, *a.traffic_record)
         return
     if a.traffic_probe:
-        traffic_probe(w, "f32" if a.config in (3, 4, 5) else "f64", B)
+        traffic_probe(w, dtype, B)
         return
-    dtype = "f32" if a.config in (3, 4, 5) else "f64"
     log(f"workload {w.name} dtype {dtype} B {B}")
     r = run_gpu(w, dtype, B, a.steps, a.warmup)
     log(f"primary: {r}")
     extra = {}
-    if a.config == 2 and not a.no_fp32:
-        w3 = synthetic.CONFIGS[3]
+    if primary and not a.no_fp32:
+        w3 = synthetic.WORKLOADS["sphere_r12_h0.2_fp32"]
         r3 = run_gpu(w3, "f32", B, a.steps, a.warmup)
         log(f"fp32: {r3}")
-        extra["cfg3_fp32"] = {k: r3[k] for k in ("ptstates_per_s", "gflops", "t_step",
+        extra[w3.name] = {k: r3[k] for k in ("ptstates_per_s", "gflops", "t_step",
                                                  "t_kernel", "achieved_gbs", "frac")}
     eig = None
-    if a.config == 2 and not a.no_eig:
+    if primary and not a.no_eig:
         eig = eigensolve_compare()
         log(f"eigensolve: {eig}")
     lrn = None
-    if a.config == 2 and not a.no_learned:
+    if primary and not a.no_learned:
         log("learned preconditioner: periodic workload")
-        lrn = learned_compare(synthetic.CONFIGS[4])
+        lrn = learned_compare(synthetic.WORKLOADS["periodic96_h0.25"])
         log(f"learned: {lrn}")
     cpu = None
     if not a.no_cpu:

@@ -25,7 +25,7 @@ Preconditioner for a residual r of a state with shift sigma < 0:
 so K(-r) = -K(r) and K(c r) = c K(r) for c > 0.  Training pairs are
 (r, x = (T - sigma)^-1 r) with sigma = -<psi|T|psi>.  The loss of a batch
 measures the error in the energy norm of A_i = T - sigma_i (the norm in which
-a preconditioner is judged: an error at wave number k weighs k^2/2 - sigma,
+a preconditioner is measured: an error at wave number k weighs k^2/2 - sigma,
 so wrong short-wavelength output, which the plain L2 norm of the smooth
 target barely sees, is penalised):
     L = sum_i <e_i|A_i|e_i> / sum_i <t_i|A_i|t_i>,  e_i = M (g_i f(u_i) - t_i),

@@ -24,7 +24,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Workload", "CONFIGS", "make_config", "draw_atoms", "draw_states",
+    "Workload", "WORKLOADS", "make_workload", "draw_atoms", "draw_states",
     "wells_potential", "harmonic_potential",
 ]
 
@@ -61,28 +61,28 @@ class Workload:
         return self.n * self.h
 
 
-# The five workloads: (1) harmonic box, (2) sphere FP64, (3) the same sphere
-# in FP32 / split precision, (4) periodic box for the learned preconditioner,
-# (5) large sphere with a cage of atoms.
-CONFIGS = {
-    1: Workload("box32_harmonic", "box", 0.3, n=32, nstates=8, block=8, seed=1,
-                potential="harmonic"),
-    2: Workload("sphere_r12_h0.2", "sphere", 0.2, radius=12.0, nstates=128,
-                block=32, seed=2, nat=16, atom_layout="ball", atom_radius=8.0),
-    3: Workload("sphere_r12_h0.2_fp32", "sphere", 0.2, radius=12.0, nstates=128,
-                block=32, seed=2, nat=16, atom_layout="ball", atom_radius=8.0),
-    4: Workload("periodic96_h0.25", "periodic", 0.25, n=96, nstates=256,
-                block=32, seed=4, nat=32, atom_layout="box"),
-    5: Workload("sphere_r18_h0.18_cage60", "sphere", 0.18, radius=18.0,
-                nstates=240, block=64, seed=5, nat=60, atom_layout="cage",
-                atom_radius=6.7),
-}
+# The workloads, by name: a harmonic box, a sphere in FP64, the same sphere
+# in FP32 / split precision, a periodic box for the learned preconditioner,
+# and a large sphere with a cage of atoms.
+WORKLOADS = {w.name: w for w in (
+    Workload("box32_harmonic", "box", 0.3, n=32, nstates=8, block=8, seed=1,
+             potential="harmonic"),
+    Workload("sphere_r12_h0.2", "sphere", 0.2, radius=12.0, nstates=128,
+             block=32, seed=2, nat=16, atom_layout="ball", atom_radius=8.0),
+    Workload("sphere_r12_h0.2_fp32", "sphere", 0.2, radius=12.0, nstates=128,
+             block=32, seed=2, nat=16, atom_layout="ball", atom_radius=8.0),
+    Workload("periodic96_h0.25", "periodic", 0.25, n=96, nstates=256,
+             block=32, seed=4, nat=32, atom_layout="box"),
+    Workload("sphere_r18_h0.18_cage60", "sphere", 0.18, radius=18.0,
+             nstates=240, block=64, seed=5, nat=60, atom_layout="cage",
+             atom_radius=6.7),
+)}
 
 
-def make_config(idx: int, **overrides) -> Workload:
-    """Return a copy of workload ``idx`` with fields overridden (for small
+def make_workload(name: str, **overrides) -> Workload:
+    """Return a copy of workload ``name`` with fields overridden (for small
     test-sized variants of the same recipe)."""
-    return dataclasses.replace(CONFIGS[idx], **overrides)
+    return dataclasses.replace(WORKLOADS[name], **overrides)
 
 
 @dataclasses.dataclass

@@ -71,14 +71,15 @@ def test_index_map_bit_exact(args):
 
 
 @pytest.mark.parametrize("cfg", [
-    dict(idx=2, radius=4.0, nat=5, atom_radius=2.5),
-    dict(idx=2),
-    dict(idx=4, n=24, nat=6),
-    dict(idx=5, radius=9.0, nat=60, atom_radius=6.7, rc=1.2),
+    dict(name="sphere_r12_h0.2", radius=4.0, nat=5, atom_radius=2.5),
+    dict(name="sphere_r12_h0.2"),
+    dict(name="periodic96_h0.25", n=24, nat=6),
+    dict(name="sphere_r18_h0.18_cage60", radius=9.0, nat=60, atom_radius=6.7, rc=1.2),
 ])
 def test_projector_sets_match_oracle(cfg):
-    idx = cfg.pop("idx")
-    w = synthetic.make_config(idx, **cfg)
+    cfg = dict(cfg)
+    name = cfg.pop("name")
+    w = synthetic.make_workload(name, **cfg)
     og = ogrid.grid_for(w)
     atoms = synthetic.draw_atoms(w)
     ops = okb.build_projectors(og, atoms.pos, atoms.D, w.rc, w.sigma)

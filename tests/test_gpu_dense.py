@@ -20,7 +20,7 @@ def need_gpu():
 
 @pytest.fixture(scope="module")
 def small():
-    w = synthetic.make_config(2, radius=3.0, nat=5, atom_radius=2.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=3.0, nat=5, atom_radius=2.0)
     og, atoms, H = hamiltonian.build_system(w)
     g = rsd.Grid.for_workload(w)
     ctx = rsd.Context(g, 256)
@@ -178,7 +178,7 @@ def test_subspace_diag_fp64(small):
 def test_full_size_overlap():
     """Config-2 grid (0.9M points), 128 states: FP64 overlap and the split
     BF16 overlap of the FP32 copy."""
-    w = synthetic.CONFIGS[2]
+    w = synthetic.WORKLOADS["sphere_r12_h0.2"]
     g = rsd.Grid.for_workload(w)
     ctx = rsd.Context(g, 128)
     x = synthetic.draw_states(synthetic.rng_after_atoms(w), 128, g.np)

@@ -35,7 +35,7 @@ def _setup(w, N, B, dtype=np.float64, **kw):
 def test_one_step_matches_oracle(m):
     """The same step on the same orthonormal input: eigenvalues, residual norms
     and the updated states agree with the oracle's implementation."""
-    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2)
     N, B = 16, 8
     og, H, g, solver, psi = _setup(w, N, B, m=m, tol=1e-12)
     # a few oracle steps first so the states are not random noise
@@ -52,7 +52,7 @@ def test_one_step_matches_oracle(m):
 
 
 def test_block_stop_freezes_converged_blocks():
-    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2)
     N, B = 16, 8
     og, H, g, solver, psi = _setup(w, N, B, tol=1e9)
     t = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
@@ -66,7 +66,7 @@ def test_block_stop_freezes_converged_blocks():
 
 def test_converges_harmonic_box():
     """Lowest four levels of the 32^3 harmonic box from random states."""
-    w = synthetic.make_config(1, nstates=4)
+    w = synthetic.make_workload("box32_harmonic", nstates=4)
     og, H, g, solver, psi = _setup(w, 4, 4, tol=1e-9)
     t = torch.from_numpy(rsd.to_blocks(psi, 4)).to(DEV)
     want = np.array([1.4999991750, 2.4999964915, 2.4999964915, 2.4999964915])
@@ -82,7 +82,7 @@ def test_converges_harmonic_box():
 def test_converges_dense_bruteforce(dtype, etol):
     """Tiny sphere with wells and projectors: lowest eigenvalues of the dense
     matrix; the FP32 / split-precision solve reaches them to 1e-6 Ha."""
-    w = synthetic.make_config(2, radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
     og, H, g, solver, psi = _setup(w, 8, 8, dtype=dtype, tol=1e-9 if dtype == np.float64 else 1e-5)
     ev = np.linalg.eigvalsh(H.dense())[:8]
     t = torch.from_numpy(rsd.to_blocks(psi.astype(dtype), 8)).to(DEV)
@@ -99,7 +99,7 @@ def test_partial_last_block_step_matches_oracle():
     """12 states in blocks of 8: the last block holds 4 zero padding states.
     The step agrees with the oracle's on the 12 states (whose stopping rule
     sees a block of 4), and the padding stays exactly zero."""
-    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2)
     N, B = 12, 8
     og, H, g, solver, psi = _setup(w, N, B, tol=1e-12)
     opts = rmmdiis.Options(m=3, block=B, tol=1e-12)
@@ -122,7 +122,7 @@ def test_partial_last_block_step_matches_oracle():
 def test_partial_last_block_converges(dtype, etol):
     """6 states in blocks of 4 (two padding states) reach the lowest six
     eigenvalues of the dense matrix of a tiny sphere."""
-    w = synthetic.make_config(2, radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
     og, H, g, solver, psi = _setup(w, 6, 4, dtype=dtype, tol=1e-9 if dtype == np.float64 else 1e-5)
     ev = np.linalg.eigvalsh(H.dense())[:6]
     t = torch.from_numpy(rsd.to_blocks(psi.astype(dtype), 4)).to(DEV)
@@ -140,7 +140,7 @@ def test_cage_workload_full_size_steps():
     """The largest workload (sphere R 18 at h 0.18, 4.19M points, 60 atoms on
     a cage), 240 FP32 states in blocks of 64 (one padded block): three steps
     run, keep the padding zero, and lower every Rayleigh-Ritz value."""
-    w = synthetic.CONFIGS[5]
+    w = synthetic.WORKLOADS["sphere_r18_h0.18_cage60"]
     g = rsd.Grid.for_workload(w)
     atoms = synthetic.draw_atoms(w)
     v = synthetic.potential_for(w, g.xyz(), atoms)
@@ -159,7 +159,7 @@ def test_cage_workload_full_size_steps():
 
 
 def test_bad_solver_arguments_raise():
-    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.2)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2)
     g = rsd.Grid.for_workload(w)
     v = torch.zeros(g.np, dtype=torch.float64, device=DEV)
     for n, B in ((0, 8), (257, 8), (16, 3), (16, 128)):

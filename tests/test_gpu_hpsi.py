@@ -49,7 +49,7 @@ def _relerr(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-SMALL = synthetic.make_config(2, radius=3.0, nat=5, atom_radius=2.0)
+SMALL = synthetic.make_workload("sphere_r12_h0.2", radius=3.0, nat=5, atom_radius=2.0)
 
 
 @pytest.mark.parametrize("B", [1, 2, 4, 8, 16, 32, 64])
@@ -73,12 +73,12 @@ def test_hpsi_fp32_sphere(B):
 
 
 def test_hpsi_box_harmonic_and_periodic():
-    w = synthetic.CONFIGS[1]
+    w = synthetic.WORKLOADS["box32_harmonic"]
     og, H, g, nl = _system(w)
     psi = _states(w, 8, og.np, np.float64)
     got = _gpu_hpsi(g, nl, H.vloc, psi, 8, np.float64)
     assert _relerr(got, H.apply(psi)) < 1e-12
-    wp = synthetic.make_config(4, n=24, nat=4)
+    wp = synthetic.make_workload("periodic96_h0.25", n=24, nat=4)
     og, H, g, nl = _system(wp)
     psi = _states(wp, 64, og.np, np.float64)
     got = _gpu_hpsi(g, nl, H.vloc, psi, 32, np.float64)
@@ -94,9 +94,9 @@ def test_hpsi_fp64_march_lattice_edges(kind, n, nat):
     are read as neighbours, never written); the Dirichlet box has partial
     bricks on every face."""
     if kind == "periodic":
-        w = synthetic.make_config(4, n=n, nat=nat, rc=1.5)
+        w = synthetic.make_workload("periodic96_h0.25", n=n, nat=nat, rc=1.5)
     else:
-        w = synthetic.make_config(1, n=n)
+        w = synthetic.make_workload("box32_harmonic", n=n)
     og, H, g, nl = _system(w)
     psi = _states(w, 64, og.np, np.float64)
     want = H.apply(psi)
@@ -106,7 +106,7 @@ def test_hpsi_fp64_march_lattice_edges(kind, n, nat):
 
 
 def test_overlapping_spheres_no_race():
-    w = synthetic.make_config(2, radius=2.4, nat=8, atom_radius=0.8, rc=1.5)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=8, atom_radius=0.8, rc=1.5)
     og, H, g, nl = _system(w)
     assert nl.ncolours >= 3
     psi = _states(w, 32, og.np, np.float64)
@@ -140,7 +140,7 @@ def test_project_and_apply_nl(dtype, tol):
 def test_full_size_sphere_sampled(dtype, tol):
     """Config-2 grid (0.9M points, 16 atoms), all 128 states in blocks of 32,
     checked at sampled points computed one by one by the oracle."""
-    w = synthetic.CONFIGS[2]
+    w = synthetic.WORKLOADS["sphere_r12_h0.2"]
     og, atoms, H = hamiltonian.build_system(w)
     g = rsd.Grid.for_workload(w)
     nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=128)
@@ -158,12 +158,12 @@ def test_full_size_sphere_sampled(dtype, tol):
     assert _relerr(got[:, pts], want) < tol
 
 
-@pytest.mark.parametrize("cfg,N,B", [(4, 64, 32), (5, 64, 64)])
-def test_full_size_periodic_and_cage_sampled(cfg, N, B):
-    """Config 4 (periodic 96^3, 32 atoms, minimum image) and config 5 (sphere
-    R 18 at h 0.18, 4.19M points, 60 atoms on a cage) in FP32, N states,
-    checked at sampled points (grid-wide and inside projector spheres)."""
-    w = synthetic.CONFIGS[cfg]
+@pytest.mark.parametrize("name,seed,N,B", [("periodic96_h0.25", 4, 64, 32), ("sphere_r18_h0.18_cage60", 5, 64, 64)])
+def test_full_size_periodic_and_cage_sampled(name, seed, N, B):
+    """The periodic 96^3 box (32 atoms, minimum image) and the sphere R 18 at
+    h 0.18 (4.19M points, 60 atoms on a cage) in FP32, N states, checked at
+    sampled points (grid-wide and inside projector spheres)."""
+    w = synthetic.WORKLOADS[name]
     og, atoms, H = hamiltonian.build_system(w)
     g = rsd.Grid.for_workload(w)
     assert g.np == og.np
@@ -172,7 +172,7 @@ def test_full_size_periodic_and_cage_sampled(cfg, N, B):
     v = H.vloc.astype(np.float32)
     got = _gpu_hpsi(g, nl, v, psi, B, np.float32)
     x64 = psi.astype(np.float64)
-    rng = np.random.default_rng(cfg)
+    rng = np.random.default_rng(seed)
     pts = rng.choice(og.np, 300, replace=False)
     sph = np.concatenate(H.proj.idx)
     pts = np.unique(np.concatenate([pts, rng.choice(sph, 200, replace=False)]))

@@ -27,7 +27,7 @@ def need_gpu():
 
 
 def _system():
-    w = synthetic.make_config(4, n=32, nat=4, nstates=32, block=32)
+    w = synthetic.make_workload("periodic96_h0.25", n=32, nat=4, nstates=32, block=32)
     g = rsd.Grid.for_workload(w)
     atoms = synthetic.draw_atoms(w)
     v = synthetic.potential_for(w, g.xyz(), atoms)

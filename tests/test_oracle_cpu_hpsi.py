@@ -14,7 +14,7 @@ def lib():
 
 @pytest.mark.parametrize("B", [1, 4, 32])
 def test_cpu_hpsi_matches_python(lib, B):
-    w = synthetic.make_config(2, radius=2.4, nat=3, atom_radius=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.0)
     g, _, H = hamiltonian.build_system(w)
     rng = np.random.default_rng(B)
     nblk = 2

@@ -50,7 +50,7 @@ def test_sphere_membership_inclusive_and_count():
 
 
 def test_hermitian_and_rank_with_overlaps():
-    w = synthetic.make_config(2, radius=1.6, h=0.25, nat=3, atom_radius=0.6, rc=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.25, nat=3, atom_radius=0.6, rc=1.0)
     g, atoms, H = hamiltonian.build_system(w)
     ps = H.proj
     assert ps.colour.max() >= 1          # spheres overlap, so >= 2 colours
@@ -64,7 +64,7 @@ def test_hermitian_and_rank_with_overlaps():
 
 
 def test_coloured_scatter_equals_plain_sum():
-    w = synthetic.make_config(2, radius=3.0, nat=6, atom_radius=1.5)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=3.0, nat=6, atom_radius=1.5)
     g, atoms, H = hamiltonian.build_system(w)
     ps = H.proj
     rng = np.random.default_rng(4)

@@ -38,7 +38,7 @@ def test_cholesky_matches_lapack_and_reports_pivot():
 
 
 def test_rayleigh_ritz_matches_eigh_and_diagonalises():
-    w = synthetic.make_config(2, radius=1.6, h=0.25, nat=2, atom_radius=0.6, rc=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.25, nat=2, atom_radius=0.6, rc=1.0)
     g, atoms, H = hamiltonian.build_system(w)
     rng = np.random.default_rng(2)
     psi, _, _ = linalg.orthonormalize(rng.uniform(-1, 1, size=(6, g.np)), g.dv)

@@ -34,7 +34,7 @@ def test_filter_zero_outside_domain():
 
 
 def test_trial_lambda_minimises_rayleigh_quotient():
-    w = synthetic.make_config(2, radius=1.6, h=0.25, nat=2, atom_radius=0.6, rc=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.25, nat=2, atom_radius=0.6, rc=1.0)
     g, _, H = hamiltonian.build_system(w)
     rng = np.random.default_rng(7)
     dv = g.dv
@@ -69,7 +69,7 @@ def test_diis_coefficients_minimise_ratio():
 def test_converged_eigenvalues_harmonic_box():
     """Lowest four levels of the 32^3 harmonic box (exact discrete values from
     the separable 1-D problems) from random starts."""
-    w = synthetic.make_config(1, nstates=4)
+    w = synthetic.make_workload("box32_harmonic", nstates=4)
     g, _, H = hamiltonian.build_system(w)
     psi = synthetic.draw_states(synthetic.rng_after_atoms(w), 4, g.np)
     psi, hist = rmmdiis.eigensolve(H, psi, rmmdiis.Options(block=4, tol=1e-9), 120)
@@ -81,7 +81,7 @@ def test_converged_eigenvalues_harmonic_box():
 def test_converged_eigenvalues_dense_bruteforce():
     """Tiny sphere with wells and projectors: the eigensolver reaches the
     lowest eigenvalues of the assembled dense matrix."""
-    w = synthetic.make_config(2, radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.2, nat=2, atom_radius=0.6, rc=1.0)
     g, _, H = hamiltonian.build_system(w)
     ev = np.linalg.eigvalsh(H.dense())
     psi = synthetic.draw_states(synthetic.rng_after_atoms(w), 4, g.np)
@@ -90,7 +90,7 @@ def test_converged_eigenvalues_dense_bruteforce():
 
 
 def test_step_keeps_orthonormality_and_block_stop():
-    w = synthetic.make_config(2, radius=2.0, nat=2, atom_radius=0.8)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.0, nat=2, atom_radius=0.8)
     g, _, H = hamiltonian.build_system(w)
     psi = synthetic.draw_states(synthetic.rng_after_atoms(w), 8, g.np)
     psi, _, _ = linalg.orthonormalize(psi, g.dv)

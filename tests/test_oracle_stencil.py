@@ -97,7 +97,7 @@ def test_config1_separable_operator():
     """The star stencil and V = r^2/2 are sums of 1-D operators: products of
     1-D eigenvectors are eigenvectors of the 3-D operator with summed
     eigenvalues."""
-    w = synthetic.CONFIGS[1]
+    w = synthetic.WORKLOADS["box32_harmonic"]
     g, _, H = hamiltonian.build_system(w)
     e, v = _one_d_harmonic()
     u = g.inner          # integer coordinates 0..31 per axis
@@ -116,7 +116,7 @@ def test_config1_separable_operator():
 
 
 def test_local_at_matches_full():
-    w = synthetic.make_config(2, radius=2.0, nat=0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.0, nat=0)
     g, _, H = hamiltonian.build_system(w)
     rng = np.random.default_rng(0)
     psi = rng.uniform(-1, 1, size=(3, g.np))
@@ -127,7 +127,7 @@ def test_local_at_matches_full():
 
 
 def test_hermitian_local():
-    w = synthetic.make_config(2, radius=2.2, nat=0)
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.2, nat=0)
     g, _, H = hamiltonian.build_system(w)
     rng = np.random.default_rng(1)
     a, b = rng.uniform(-1, 1, size=(2, g.np))
