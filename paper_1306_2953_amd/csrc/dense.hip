@@ -806,30 +806,67 @@ cholesky_kernel(const double *__restrict__ S, double *__restrict__ Wg, double *_
 }
 
 // Inverse of an upper-triangular U: one wave per column j solves U t = e_j
-// by back substitution, the inner products split over the 64 lanes and
-// summed in a fixed order; the column is kept in LDS.  T = U^-1 is upper
-// triangular.  Skipped when info != 0.
+// by back substitution.  T = U^-1 is upper triangular.  Skipped when
+// info != 0.
+//  - LDSU (N <= 128): column-oriented.  U^T is staged in LDS; lane l keeps
+//    the running sums s_m = sum_(k > m) U[m][k] t_k of rows m = l, l + 64;
+//    for k = j down to 0, t_k = -s_k / U[k][k] (t_j = 1 / U[j][j]) is read
+//    from the lane that owns row k, and every lane adds U[m][k] t_k to its
+//    rows m < k.  Each step is one broadcast instead of a wave reduction;
+//    the sums run in a fixed order (k descending).
+//  - otherwise: row-oriented, the inner products split over the 64 lanes
+//    and summed in a fixed butterfly, U read from global memory.
+constexpr size_t kTrinvLds = 128 * 128 * sizeof(double);
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <bool LDSU>
 __global__ void __launch_bounds__(1024)
 trinv_kernel(const double *__restrict__ U, double *__restrict__ T, int N, const int *__restrict__ info) {
-    __shared__ double col[16][256];
+    extern __shared__ double ut[];              // LDSU: U^T [N][N]
+    __shared__ double cols[LDSU ? 1 : 16 * 256];
     if (*info) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    double *t = col[wave];
-    for (int j = wave; j < N; j += nw) {
-        for (int i = lane; i < N; i += 64) t[i] = 0.0;
-        if (lane == 0) t[j] = 1.0 / U[j * N + j];
-        __builtin_amdgcn_wave_barrier();
-        for (int i = j - 1; i >= 0; --i) {
-            double s = 0.0;
-            for (int k = i + 1 + lane; k <= j; k += 64) s += U[i * N + k] * t[k];
-            s = wave_sum(s);
-            if (lane == 0) t[i] = -s / U[i * N + i];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if constexpr (LDSU) {
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) ut[(e % N) * N + e / N] = U[e];
+        __syncthreads();
+        for (int j = wave; j < N; j += nw) {
+            double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+            for (int k = j; k >= 0; --k) {
+                const double sk = readlane_f64(k < 64 ? s0 : s1, k & 63);
+                const double ukk = ut[k * N + k];
+                const double tk = k == j ? 1.0 / ukk : -sk / ukk;
+                if (lane == (k & 63)) {
+                    if (k < 64) t0 = tk;
+                    else t1 = tk;
+                }
+                if (lane < k) s0 += ut[k * N + lane] * tk;
+                if (lane + 64 < k) s1 += ut[k * N + lane + 64] * tk;
+            }
+            if (lane < N) T[lane * N + j] = lane <= j ? t0 : 0.0;
+            if (lane + 64 < N) T[(lane + 64) * N + j] = lane + 64 <= j ? t1 : 0.0;
         }
-        for (int i = lane; i < N; i += 64) T[i * N + j] = t[i];
-        __builtin_amdgcn_wave_barrier();
+    } else {
+        double *t = cols + wave * 256;
+        for (int j = wave; j < N; j += nw) {
+            for (int i = lane; i < N; i += 64) t[i] = 0.0;
+            if (lane == 0) t[j] = 1.0 / U[j * N + j];
+            __builtin_amdgcn_wave_barrier();
+            for (int i = j - 1; i >= 0; --i) {
+                double s = 0.0;
+                for (int k = i + 1 + lane; k <= j; k += 64) s += U[i * N + k] * t[k];
+                s = wave_sum(s);
+                if (lane == 0) t[i] = -s / U[i * N + i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            for (int i = lane; i < N; i += 64) T[i * N + j] = t[i];
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 }
 
@@ -1242,7 +1279,14 @@ rs_status cholesky(DenseWork &w, const double *S, double *U, int N, int *info_de
 }
 
 rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStream_t st) {
-    hipLaunchKernelGGL(trinv_kernel, dim3(1), dim3(1024), 0, st, U, T, N, info_dev);
+    if (N <= 128) {
+        RS_HIP(hipFuncSetAttribute((const void *)trinv_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kTrinvLds));
+        const size_t lds = (size_t)N * N * sizeof(double);
+        hipLaunchKernelGGL(trinv_kernel<true>, dim3(1), dim3(1024), lds, st, U, T, N, info_dev);
+    } else {
+        hipLaunchKernelGGL(trinv_kernel<false>, dim3(1), dim3(1024), 0, st, U, T, N, info_dev);
+    }
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
