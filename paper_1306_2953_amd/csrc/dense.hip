@@ -1208,12 +1208,9 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
             hipLaunchKernelGGL((rotate_f64_px_kernel<RS_ROT_MT>), dim3(grid), dim3(512), xl, st, (double *)psi, Xm, np,
                                B, N, ncb, ntiles, skip);
         } else if (RS_ROT_VEC && B % 16 == 0) {
-            if (ncb <= 8)
-                hipLaunchKernelGGL((rotate_f64_vec_kernel<2, 8>), dim3((unsigned)((np + 255) / 256)), dim3(512), lds,
-                                   st, (double *)psi, Xm, np, B, N, ncb, skip);
-            else
-                hipLaunchKernelGGL((rotate_f64_vec_kernel<1, MAXC64>), dim3((unsigned)((np + 127) / 128)), dim3(512),
-                                   lds, st, (double *)psi, Xm, np, B, N, ncb, skip);
+            // ncb > 8 here: the persistent kernel above takes the rest
+            hipLaunchKernelGGL((rotate_f64_vec_kernel<1, MAXC64>), dim3((unsigned)((np + 127) / 128)), dim3(512),
+                               lds, st, (double *)psi, Xm, np, B, N, ncb, skip);
         } else if (ncb <= 8) {
             const unsigned g2 = (unsigned)((np + 255) / 256);
             hipLaunchKernelGGL((rotate_f64_lds_kernel<2, 8>), dim3(g2), dim3(512), lds, st, (double *)psi, Xm, np, B, N,
