@@ -406,7 +406,7 @@ def main():
                          "three H psi applications of the workload; prints nothing")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the H psi path and eigensolver run on one GPU (no multi-GPU sharding is implemented); --gpus must be 1"}))
         sys.exit(2)
     w = synthetic.WORKLOADS[a.workload]
     B = a.block or w.block
