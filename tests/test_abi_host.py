@@ -92,3 +92,17 @@ def test_projector_sets_match_oracle(cfg):
     gam = np.concatenate(ops.gamma)
     assert np.max(np.abs(ex["gamma"] - gam)) <= 1e-14 * np.max(np.abs(gam))
     assert np.array_equal(ex["colour"], ops.colour)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; a request for more exits with status 2
+    and a JSON error line before touching any device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "--gpus must be 1" in msg["error"]
