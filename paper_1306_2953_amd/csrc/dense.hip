@@ -757,48 +757,40 @@ rotate_bf16x3_px_kernel(float *__restrict__ psi, const unsigned short *__restric
 // ------------------------------------------------------------- Cholesky
 // S = U^T U, U upper with positive diagonal (right-looking, one work-group;
 // the working copy W lives in LDS when it fits, else in global memory).
-// info = 0, or the 1-based column whose pivot is not positive (nothing after
-// it is computed).
+// Thread (c, g) owns the columns j = c (mod 128) and the rows i = g (mod
+// nt/128) of the trailing update, so no index is divided.  Step k reads only
+// row k of W (unscaled: the update subtracts W[k][i] W[k][j] / d) and writes
+// only rows below it, so a step needs one barrier; row k of U goes straight
+// to U.  Every thread reads the same pivot d, so all leave the loop together
+// on a bad pivot.  info = 0, or the 1-based column whose pivot is not
+// positive (that row of U and all after it stay zero).
 template <bool LDSW>
 __global__ void __launch_bounds__(1024)
 cholesky_kernel(const double *__restrict__ S, double *__restrict__ Wg, double *__restrict__ U, int N,
                 int *__restrict__ info) {
     extern __shared__ double ldsW[];
-    __shared__ double piv;
-    __shared__ int bad;
     double *W = LDSW ? ldsW : Wg;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int c = tid & 127, g = tid >> 7, ng = nt >> 7;
     for (int e = tid; e < N * N; e += nt) {
         W[e] = S[e];
         U[e] = 0.0;
     }
-    if (tid == 0) bad = 0;
     __syncthreads();
+    int bad = 0;
     for (int k = 0; k < N; ++k) {
-        if (tid == 0) {
-            const double d = W[k * N + k];
-            if (!(d > 0.0) || !isfinite(d)) {
-                bad = k + 1;
-            } else {
-                piv = sqrt(d);
-                U[k * N + k] = piv;
-                W[k * N + k] = piv;
-            }
+        const double d = W[k * N + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            bad = k + 1;
+            break;
         }
-        __syncthreads();
-        if (bad) break;
-        const double inv = 1.0 / piv;
-        for (int j = k + 1 + tid; j < N; j += nt) {
-            const double u = W[k * N + j] * inv;
-            W[k * N + j] = u;          // row k of W now holds row k of U
-            U[k * N + j] = u;
-        }
-        __syncthreads();
-        // trailing update of the upper triangle: W[i][j] -= U[k][i] U[k][j]
-        const int m = N - k - 1;
-        for (int e = tid; e < m * m; e += nt) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j >= i) W[i * N + j] -= W[k * N + i] * W[k * N + j];
+        const double piv = sqrt(d), inv = 1.0 / piv, invd = 1.0 / d;
+        for (int j = c; j < N; j += 128) {
+            if (j < k) continue;
+            const double wkj = W[k * N + j];
+            if (g == 0) U[k * N + j] = j == k ? piv : wkj * inv;
+            const double f = wkj * invd;
+            for (int i = k + 1 + g; i <= j; i += ng) W[i * N + j] -= W[k * N + i] * f;
         }
         __syncthreads();
     }

@@ -71,21 +71,29 @@ def test_overlap_bf16x3_error_bound(small, nblk, B):
         assert np.all(np.abs(got - want) <= bound)
 
 
-def test_cholesky_and_pivot(small):
+@pytest.mark.parametrize("N", [1, 37, 100, 128, 200])
+def test_cholesky_and_pivot(small, N):
+    """N <= 130 keeps the working matrix in LDS, 200 runs it in global memory."""
     w, og, H, g, ctx = small
     rng = np.random.default_rng(3)
-    A = rng.normal(size=(100, 100))
-    S = A @ A.T + 100 * np.eye(100)
+    A = rng.normal(size=(N, N))
+    S = A @ A.T + N * np.eye(N)
     U, info = ctx.cholesky(_dev(S))
     torch.cuda.synchronize()
     assert int(info.item()) == 0
-    assert np.allclose(U.cpu().numpy(), np.linalg.cholesky(S).T, atol=1e-12 * np.max(np.abs(S)))
+    Ug = U.cpu().numpy()
+    assert np.all(np.tril(Ug, -1) == 0.0)
+    assert np.allclose(Ug, np.linalg.cholesky(S).T, atol=1e-12 * np.max(np.abs(S)))
     psi = rng.uniform(-1, 1, (6, 400))
     psi[4] = psi[2]
     S2 = linalg.overlap(psi, 1.0)
     S2[4, 4] -= 1e-9 * S2[2, 2]
     U, info = ctx.cholesky(_dev(S2))
     assert int(info.item()) == 5
+    Ug = U.cpu().numpy()
+    assert np.all(Ug[4:] == 0.0)            # rows from the bad pivot on are not computed
+    L4 = np.linalg.cholesky(S2[:4, :4])
+    assert np.allclose(Ug[:4, :4], L4.T, atol=1e-12 * np.max(np.abs(S2)))
 
 
 @pytest.mark.parametrize("N", [8, 37, 128, 200, 256])
