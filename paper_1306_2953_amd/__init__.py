@@ -152,17 +152,51 @@ def _dev(t, name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check(t, name: str, shape=None, dtype=None, like=None, numel=None):
+    """Refuses a tensor whose shape, dtype or device differs from what the C
+    call will read or write (the C side only sees a pointer)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if like is not None:
+        shape = tuple(like.shape) if shape is None else shape
+        dtype = like.dtype if dtype is None else dtype
+        if t.device != like.device:
+            raise ValueError(f"{name} must be on {like.device}, got {t.device}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
 def _blocks(psi, grid: Grid):
+    torch = _torch()
+    if not isinstance(psi, torch.Tensor):
+        raise TypeError("fields must be torch tensors")
     if psi.dim() != 3 or psi.shape[1] != grid.np:
         raise ValueError(f"psi must be [nblk, np={grid.np}, B], got {tuple(psi.shape)}")
-    return psi.shape[0], psi.shape[2]
+    if psi.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f"fields must be float32 or float64, got {psi.dtype}")
+    B = psi.shape[2]
+    if B < 1 or B > 64 or (B & (B - 1)):
+        raise ValueError(f"B must be a power of two in [1, 64], got {B}")
+    return psi.shape[0], B
 
 
 def hpsi_block(grid: Grid, nl: Optional[NonLocal], vloc, psi, hpsi, stream=None):
     """hpsi = (T + V + V_nl) psi for psi [nblk, np, B] (rs_hpsi_block)."""
     nblk, B = _blocks(psi, grid)
-    if hpsi.shape != psi.shape or hpsi.dtype != psi.dtype or vloc.dtype != psi.dtype:
-        raise ValueError("hpsi/vloc must match psi in shape/dtype")
+    _check(hpsi, "hpsi", like=psi)
+    _check(vloc, "vloc", dtype=psi.dtype, numel=grid.np)
+    if vloc.device != psi.device:
+        raise ValueError("vloc must be on psi's device")
+    if hpsi.data_ptr() == psi.data_ptr():
+        raise ValueError("hpsi must not alias psi")
     check(lib().rs_hpsi_block(grid.handle, nl.handle if nl is not None else None,
                               _dev(vloc, "vloc"), _dev(psi, "psi"), _dev(hpsi, "hpsi"),
                               nblk, B, _dtype_code(psi), _stream(stream)))
@@ -172,8 +206,7 @@ def hpsi_block(grid: Grid, nl: Optional[NonLocal], vloc, psi, hpsi, stream=None)
 def project_nl(grid: Grid, nl: NonLocal, psi, proj, stream=None):
     """proj [nblk, nat, 4, B] = h^3 <gamma_A,i|psi> (rs_project_nl)."""
     nblk, B = _blocks(psi, grid)
-    if tuple(proj.shape) != (nblk, nl.nat, 4, B) or proj.dtype != psi.dtype:
-        raise ValueError("proj must be [nblk, nat, 4, B] of psi's dtype")
+    _check(proj, "proj", shape=(nblk, nl.nat, 4, B), dtype=psi.dtype)
     check(lib().rs_project_nl(grid.handle, nl.handle, _dev(psi, "psi"), _dev(proj, "proj"),
                               nblk, B, _dtype_code(psi), _stream(stream)))
     return proj
@@ -182,8 +215,7 @@ def project_nl(grid: Grid, nl: NonLocal, psi, proj, stream=None):
 def apply_nl(grid: Grid, nl: NonLocal, proj, hpsi, stream=None):
     """hpsi += sum gamma D proj (rs_apply_nl)."""
     nblk, B = _blocks(hpsi, grid)
-    if tuple(proj.shape) != (nblk, nl.nat, 4, B) or proj.dtype != hpsi.dtype:
-        raise ValueError("proj must be [nblk, nat, 4, B] of hpsi's dtype")
+    _check(proj, "proj", shape=(nblk, nl.nat, 4, B), dtype=hpsi.dtype)
     check(lib().rs_apply_nl(grid.handle, nl.handle, _dev(proj, "proj"), _dev(hpsi, "hpsi"),
                             nblk, B, _dtype_code(hpsi), _stream(stream)))
     return hpsi
@@ -209,6 +241,22 @@ class Context:
             L.rs_ctx_destroy(h)
             self._h = None
 
+    def _fields(self, psi):
+        nblk, B = _blocks(psi, self.grid)
+        if nblk * B > self.max_states:
+            raise ValueError(f"{nblk * B} states exceed the context's max_states {self.max_states}")
+        return nblk, B
+
+    def _square(self, A, name):
+        torch = _torch()
+        if A.dim() != 2 or A.shape[0] != A.shape[1]:
+            raise ValueError(f"{name} must be square [N, N], got {tuple(A.shape)}")
+        N = A.shape[0]
+        if N < 1 or N > self.max_states:
+            raise ValueError(f"{name}: N must be in [1, {self.max_states}]")
+        _check(A, name, dtype=torch.float64)
+        return N
+
     @staticmethod
     def _prec(t, prec):
         if prec is not None:
@@ -217,17 +265,22 @@ class Context:
 
     def overlap(self, x, y, S=None, prec=None, stream=None):
         """S [N, N] (float64) = h^3 X^T Y (rs_overlap)."""
-        nblk, B = _blocks(x, self.grid)
+        nblk, B = self._fields(x)
+        _check(y, "y", like=x)
         torch = _torch()
+        N = nblk * B
         if S is None:
-            S = torch.empty((nblk * B, nblk * B), dtype=torch.float64, device=x.device)
+            S = torch.empty((N, N), dtype=torch.float64, device=x.device)
+        _check(S, "S", shape=(N, N), dtype=torch.float64)
         check(lib().rs_overlap(self._h, _dev(x, "x"), _dev(y, "y"), _dev(S, "S"), nblk, B,
                                _dtype_code(x), self._prec(x, prec), _stream(stream)))
         return S
 
     def rotate(self, psi, X, prec=None, stream=None):
         """psi <- psi X in place (rs_rotate)."""
-        nblk, B = _blocks(psi, self.grid)
+        nblk, B = self._fields(psi)
+        N = nblk * B
+        _check(X, "X", shape=(N, N), dtype=_torch().float64)
         check(lib().rs_rotate(self._h, _dev(psi, "psi"), _dev(X, "X"), nblk, B,
                               _dtype_code(psi), self._prec(psi, prec), _stream(stream)))
         return psi
@@ -235,7 +288,7 @@ class Context:
     def cholesky(self, S, stream=None):
         """(U, info) with S = U^T U (rs_cholesky); info is a device int32."""
         torch = _torch()
-        N = S.shape[0]
+        N = self._square(S, "S")
         U = torch.empty_like(S)
         info = torch.zeros(1, dtype=torch.int32, device=S.device)
         check(lib().rs_cholesky(self._h, _dev(S, "S"), _dev(U, "U"), N, _dev(info, "info"),
@@ -245,7 +298,7 @@ class Context:
     def eigh(self, A, stream=None):
         """(evals, V) of symmetric A (rs_eigh); A is copied, not destroyed."""
         torch = _torch()
-        N = A.shape[0]
+        N = self._square(A, "A")
         W = A.clone()
         V = torch.empty_like(A)
         ev = torch.empty(N, dtype=torch.float64, device=A.device)
@@ -255,7 +308,9 @@ class Context:
 
     def orthonormalize(self, psi, S_out=None, prec=None, stream=None):
         """psi <- psi U^-1 in place (rs_orthonormalize_block); returns info."""
-        nblk, B = _blocks(psi, self.grid)
+        nblk, B = self._fields(psi)
+        if S_out is not None:
+            _check(S_out, "S_out", shape=(nblk * B, nblk * B), dtype=_torch().float64)
         info = ctypes.c_int32(0)
         check(lib().rs_orthonormalize_block(
             self._h, _dev(psi, "psi"), nblk, B, _dtype_code(psi), self._prec(psi, prec),
@@ -265,7 +320,8 @@ class Context:
 
     def subspace_diag(self, psi, hpsi, prec=None, stream=None):
         """Rayleigh-Ritz in place (rs_subspace_diag); returns eigenvalues."""
-        nblk, B = _blocks(psi, self.grid)
+        nblk, B = self._fields(psi)
+        _check(hpsi, "hpsi", like=psi)
         torch = _torch()
         ev = torch.empty(nblk * B, dtype=torch.float64, device=psi.device)
         check(lib().rs_subspace_diag(self._h, _dev(psi, "psi"), _dev(hpsi, "hpsi"), _dev(ev, "eig"),
@@ -280,6 +336,9 @@ class Eigensolver:
     def __init__(self, grid: Grid, nl: Optional[NonLocal], vloc, nstates: int, B: int,
                  m: int = 3, alpha: float = 0.5, tol: float = 1e-6, block_stop: bool = True,
                  record: bool = False):
+        _check(vloc, "vloc", numel=grid.np)
+        if vloc.dim() != 1:
+            raise ValueError("vloc must be one-dimensional [np]")
         self.grid, self.nl, self.vloc = grid, nl, vloc     # vloc kept alive here
         self.nstates, self.B = nstates, B
         self.nblk = -(-nstates // B)          # the last block may be zero-padded
@@ -295,9 +354,7 @@ class Eigensolver:
 
     def step(self, psi, stream=None):
         """One step in place; returns (eig, resnorm, nconv) on the host."""
-        nblk, B = _blocks(psi, self.grid)
-        if nblk != self.nblk or B != self.B:
-            raise ValueError("psi does not match the solver's blocks")
+        self._own(psi)
         eig = np.empty(self.nstates)
         res = np.empty(self.nstates)
         nconv = ctypes.c_int32(0)
@@ -308,7 +365,18 @@ class Eigensolver:
 
     def orthonormalize(self, psi, stream=None):
         """Orthonormalise the states (padding states stay zero)."""
+        self._own(psi)
         check(lib().rs_eigensolve_orthonormalize(self._h, _dev(psi, "psi"), _stream(stream)))
+
+    def _own(self, psi):
+        """psi must be the solver's [nblk, np, B] blocks in its dtype."""
+        nblk, B = _blocks(psi, self.grid)
+        if nblk != self.nblk or B != self.B:
+            raise ValueError("psi does not match the solver's blocks")
+        if psi.dtype != self.dtype:
+            raise ValueError(f"psi must be {self.dtype}, got {psi.dtype}")
+        if psi.device != self.vloc.device:
+            raise ValueError("psi must be on the solver's device")
 
     def set_precond(self, cnn: Optional["Cnn"]):
         """Use the network as preconditioner (None: the filter)."""
@@ -364,8 +432,7 @@ class Cnn:
 
     def forward(self, u, periodic: bool = False, stream=None):
         torch = _torch()
-        if u.dtype != torch.float32:
-            raise TypeError("network fields are float32")
+        _check(u, "u", dtype=torch.float32)
         f = torch.empty_like(u)
         check(lib().rs_cnn_forward(self._h, _dev(u, "u"), _dev(f, "f"), int(u.shape[0]), self._dims(u),
                                    int(periodic), _stream(stream)))
@@ -374,6 +441,7 @@ class Cnn:
     def loss_grad(self, u, t, sigma, h: float, margin: int, want_du: bool = False, stream=None):
         """Returns (loss, grad [NPARAM] float32, du or None)."""
         torch = _torch()
+        self._batch(u, t, sigma)
         loss = ctypes.c_double(0.0)
         grad = np.empty(self.NPARAM, dtype=np.float32)
         du = torch.empty_like(u) if want_du else None
@@ -385,12 +453,21 @@ class Cnn:
 
     def train_step(self, u, t, sigma, h: float, margin: int, lr: float, stream=None) -> float:
         """Loss and gradient, then one Adam update; returns the loss."""
+        self._batch(u, t, sigma)
         loss = ctypes.c_double(0.0)
         check(lib().rs_cnn_loss_grad(self._h, _dev(u, "u"), _dev(t, "t"), _dev(sigma, "sigma"),
                                      int(u.shape[0]), self._dims(u), float(h), int(margin),
                                      ctypes.byref(loss), None, None, _stream(stream)))
         self.adam_step(lr, stream=stream)
         return loss.value
+
+    @staticmethod
+    def _batch(u, t, sigma):
+        torch = _torch()
+        _check(u, "u", dtype=torch.float32)
+        Cnn._dims(u)
+        _check(t, "t", like=u)
+        _check(sigma, "sigma", dtype=torch.float64, numel=int(u.shape[0]))
 
     def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
                   stream=None):
@@ -403,6 +480,7 @@ class Cnn:
 
     def precondition(self, grid: Grid, r, sigma, stream=None):
         nblk, B = _blocks(r, grid)
+        _check(sigma, "sigma", dtype=_torch().float64, numel=nblk * B)
         out = _torch().empty_like(r)
         check(lib().rs_cnn_precondition(self._h, grid.handle, _dev(r, "r"), _dev(sigma, "sigma"),
                                         _dev(out, "out"), nblk, B, _dtype_code(r), _stream(stream)))
@@ -412,7 +490,12 @@ class Cnn:
         """desc [ncrops, 4] = (state, x0, y0, z0); returns (u, t) [ncrops, *dims]."""
         torch = _torch()
         nblk, B = _blocks(r, grid)
+        _check(x, "x", like=r)
         d = np.ascontiguousarray(desc, dtype=np.int32)
+        if d.ndim != 2 or d.shape[1] != 4:
+            raise ValueError("desc must be [ncrops, 4]")
+        if len(dims) != 3:
+            raise ValueError("dims must be (Z, Y, X)")
         n = d.shape[0]
         u = torch.empty((n,) + tuple(dims), dtype=torch.float32, device="cuda")
         t = torch.empty_like(u)
@@ -433,6 +516,7 @@ class Cnn:
 def shifted_solve(grid: Grid, r, sigma, tol: float = 1e-8, maxit: int = 2000, stream=None):
     """x = (T - sigma)^-1 r per state by conjugate gradients; returns (x, iterations)."""
     nblk, B = _blocks(r, grid)
+    _check(sigma, "sigma", dtype=_torch().float64, numel=nblk * B)
     x = _torch().empty_like(r)
     it = ctypes.c_int32(0)
     check(lib().rs_shifted_solve(grid.handle, _dev(r, "r"), _dev(sigma, "sigma"), _dev(x, "x"), nblk, B,
