@@ -258,6 +258,10 @@ typedef struct {
     int32_t block_stop;  /* nonzero: freeze blocks whose states are all < tol */
     int32_t record;      /* nonzero: keep R0 and sigma of each step for
                             rs_eigensolve_residuals (training data)          */
+    int32_t rr_sweeps;   /* Jacobi sweep cap of the step's Rayleigh-Ritz
+                            problem, 1..30; 0 (default): 30, i.e. sweeps run
+                            until the off-diagonal norm is below 1e-15 of the
+                            matrix norm (converged to FP64 accuracy)          */
 } rs_solver_opts;
 
 /* nstates (<= 256) states of dtype in nblk = ceil(nstates / B) blocks on
@@ -267,7 +271,7 @@ typedef struct {
  * zero states: they stay zero, get identity pivots in the orthonormalisation
  * and are left out of the Rayleigh-Ritz problem, the stopping rule and the
  * outputs.  opts NULL: m = 3, alpha = 1/2,
- * tol = 1e-6, block_stop = 1, record = 0.  Allocates all workspaces (about 2(m+1)+3
+ * tol = 1e-6, block_stop = 1, record = 0, rr_sweeps = 0.  Allocates all workspaces (about 2(m+1)+3
  * field arrays of np * nstates elements). */
 rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc,
                                int32_t nstates, int32_t B, int32_t dtype,
@@ -373,9 +377,23 @@ rs_status rs_shifted_solve(const rs_grid *g, const void *r, const double *sigma,
 
 /* Use the network as the solver's preconditioner (NULL: the filter).  Each
  * step then also applies the kinetic stencil to psi for the shifts
- * sigma_k = -<psi_k|T|psi_k>; a state whose <r|K r> is not positive and
- * finite falls back to the filter.  The handle must outlive its use. */
+ * sigma_k = -<psi_k|T|psi_k>.  The filter stays the fallback and the judge,
+ * per state: a state takes the filter's direction in a step where <r|K r>
+ * is not positive and finite, and takes it for good (until the next
+ * rs_eigensolve_set_precond) once its residual norm exceeds twice the
+ * smallest residual norm it has had since the network was set.  The handle
+ * must outlive its use. */
 rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c);
+
+/* Counters of the last rs_eigensolve_step. */
+typedef struct {
+    int32_t steps;          /* steps taken by this solver                      */
+    int32_t rr_sweeps;      /* Jacobi sweeps of its Rayleigh-Ritz problem      */
+    int32_t frozen_blocks;  /* blocks frozen by the stopping rule              */
+    int32_t net_states;     /* states still preconditioned by the network (0
+                               when the filter is the preconditioner)          */
+} rs_solver_stats;
+rs_status rs_eigensolve_stats(const rs_solver *s, rs_solver_stats *out);
 
 /* With opts.record: the last step's residuals R0 (after Rayleigh-Ritz) and
  * shifts sigma_k = -<psi_k|T|psi_k> into R (DEVICE, the psi layout) and

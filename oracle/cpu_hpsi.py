@@ -77,3 +77,32 @@ class CpuHamiltonian:
                 ptr(self.vloc), ptr(x), ptr(y), self.nat, ptr(self.sph_ptr),
                 ptr(self.sph_idx), ptr(self.gamma), ptr(self.D), ptr(proj))
         return y
+
+
+class FastHamiltonian:
+    """The oracle Hamiltonian's interface (g, dv, nbr, vloc, proj, apply,
+    apply_kinetic) with ``apply`` done by the C kernel above, for oracle
+    iterations on grids where the numpy operator is slow.  Same operator,
+    same FP64 arithmetic (the C kernel is checked against the numpy one)."""
+
+    def __init__(self, H):
+        self.H = H
+        self.g, self.vloc, self.proj, self.nbr = H.g, H.vloc, H.proj, H.nbr
+        self.ch = CpuHamiltonian(H)
+
+    @property
+    def dv(self) -> float:
+        return self.H.dv
+
+    def apply(self, psi: np.ndarray) -> np.ndarray:
+        x = np.atleast_2d(psi)
+        N = x.shape[0]
+        out = np.empty_like(x, dtype=np.float64)
+        for j0 in range(0, N, 32):
+            j1 = min(j0 + 32, N)
+            blk = np.ascontiguousarray(x[j0:j1].T)[None]
+            out[j0:j1] = self.ch.hpsi_blocks(blk)[0].T
+        return out if psi.ndim == 2 else out[0]
+
+    def apply_kinetic(self, psi: np.ndarray) -> np.ndarray:
+        return self.H.apply_kinetic(psi)

@@ -55,12 +55,14 @@ def filter_precond(g: Grid, r: np.ndarray, nbr: Optional[np.ndarray] = None,
     if nbr is None:
         nbr = neighbour_table(g)
     x = np.atleast_2d(r)
-    xp = np.concatenate([x, np.zeros((x.shape[0], 1))], axis=1)
+    # point-major copy with a zero row for "outside": neighbour gathers are
+    # row gathers
+    xt = np.concatenate([x.T, np.zeros((1, x.shape[0]))], axis=0)
     idx = np.where(nbr[:, :, :, 0] < 0, g.np, nbr[:, :, :, 0])   # m = 1
-    s = np.zeros_like(x)
+    s = np.zeros_like(xt[:-1])
     for a in range(3):
-        s = s + (xp[:, idx[:, a, 0]] + xp[:, idx[:, a, 1]])
-    out = alpha * x + (1.0 - alpha) / 6.0 * s
+        s = s + (xt[idx[:, a, 0]] + xt[idx[:, a, 1]])
+    out = alpha * x + (1.0 - alpha) / 6.0 * s.T
     return out if r.ndim == 2 else out[0]
 
 

@@ -335,7 +335,7 @@ class Eigensolver:
 
     def __init__(self, grid: Grid, nl: Optional[NonLocal], vloc, nstates: int, B: int,
                  m: int = 3, alpha: float = 0.5, tol: float = 1e-6, block_stop: bool = True,
-                 record: bool = False):
+                 record: bool = False, rr_sweeps: int = 0):
         _check(vloc, "vloc", numel=grid.np)
         if vloc.dim() != 1:
             raise ValueError("vloc must be one-dimensional [np]")
@@ -347,6 +347,7 @@ class Eigensolver:
         o = _abi.SolverOpts()
         o.m, o.alpha, o.tol, o.block_stop = int(m), float(alpha), float(tol), int(block_stop)
         o.record = int(record)
+        o.rr_sweeps = int(rr_sweeps)
         self._h = ctypes.c_void_p()
         check(lib().rs_eigensolve_create(grid.handle, nl.handle if nl is not None else None,
                                          _dev(vloc, "vloc"), int(nstates), int(B),
@@ -367,6 +368,13 @@ class Eigensolver:
         """Orthonormalise the states (padding states stay zero)."""
         self._own(psi)
         check(lib().rs_eigensolve_orthonormalize(self._h, _dev(psi, "psi"), _stream(stream)))
+
+    def stats(self) -> dict:
+        """Counters of the last step: steps, rr_sweeps (Jacobi sweeps of its
+        Rayleigh-Ritz problem), frozen_blocks, net_states."""
+        st = _abi.SolverStats()
+        check(lib().rs_eigensolve_stats(self._h, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in _abi.SolverStats._fields_}
 
     def _own(self, psi):
         """psi must be the solver's [nblk, np, B] blocks in its dtype."""

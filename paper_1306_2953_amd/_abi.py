@@ -28,7 +28,12 @@ PF64 = ctypes.POINTER(ctypes.c_double)
 
 
 class SolverOpts(ctypes.Structure):
-    _fields_ = [("m", I32), ("alpha", F64), ("tol", F64), ("block_stop", I32), ("record", I32)]
+    _fields_ = [("m", I32), ("alpha", F64), ("tol", F64), ("block_stop", I32), ("record", I32),
+                ("rr_sweeps", I32)]
+
+
+class SolverStats(ctypes.Structure):
+    _fields_ = [("steps", I32), ("rr_sweeps", I32), ("frozen_blocks", I32), ("net_states", I32)]
 
 
 class GridDesc(ctypes.Structure):
@@ -65,6 +70,7 @@ SIGNATURES = {
     "rs_eigensolve_set_precond": (ctypes.c_int, [P, P]),
     "rs_eigensolve_orthonormalize": (ctypes.c_int, [P, P, P]),
     "rs_eigensolve_residuals": (ctypes.c_int, [P, P, P, P]),
+    "rs_eigensolve_stats": (ctypes.c_int, [P, P]),
     "rs_cnn_create": (ctypes.c_int, [I32, I64, ctypes.POINTER(P)]),
     "rs_cnn_destroy": (None, [P]),
     "rs_cnn_set_params": (ctypes.c_int, [P, P]),

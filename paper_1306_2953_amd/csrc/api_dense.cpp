@@ -56,6 +56,9 @@ extern "C" rs_status rs_ctx_create(const rs_grid *g, int32_t max_states, rs_ctx 
 
 extern "C" void rs_ctx_destroy(rs_ctx *c) { delete c; }
 
+// Jacobi sweeps of the context's last symmetric eigensolve (device int).
+const int *ctx_sweeps(const rs_ctx *c) { return c->w.sweeps.as<int>(); }
+
 extern "C" rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t nblk, int32_t B,
                                 int32_t dtype, int32_t prec, void *stream) {
     rs_status st = check(c, nblk, B, dtype, prec, "rs_overlap");

@@ -28,6 +28,7 @@ rs_status subspace_diag_capped(rs_ctx *c, void *psi, void *hpsi, double *eig, in
                                int prec, int max_sweeps, int nreal, hipStream_t st);
 rs_status orthonormalize_impl(rs_ctx *c, void *psi, int nblk, int B, int dtype, int prec, double *S_out,
                               int32_t *info, int nreal, hipStream_t s);
+const int *ctx_sweeps(const rs_ctx *c);
 
 namespace rs {
 rs_status hpsi_apply(const rs_grid *g, const rs_nl *nl, const void *vloc, const void *psi, void *hpsi,
@@ -44,10 +45,7 @@ namespace {
 using namespace rsred;
 
 constexpr int kMaxHist = 4;   // iterates kept (m <= 3)
-// Jacobi sweeps per Rayleigh-Ritz inside a step: the subspace matrix is
-// nearly diagonal once the states settle (then one or two sweeps reach full
-// accuracy); early on a partial diagonalisation is still a valid rotation.
-constexpr int kSweeps = 6;
+constexpr int kMaxSweeps = 30;  // Jacobi sweeps that reach FP64 accuracy from any start
 
 template <typename T> struct OpDots2 {   // <x|x>, <x|y>
     const T *x, *y;
@@ -327,24 +325,38 @@ __global__ void sigma_kernel(const double *__restrict__ d2, int N, double *__res
     sigma[c] = nn > 0.0 ? -d2[1 * N + c] / nn : 0.0;
 }
 
-// Keep the learned direction d where <r|d> (rd[N + c]) is positive and
-// finite, else take the filter's alt.
+// Keep the learned direction d where the state still uses the network and
+// <r|d> (rd[N + c]) is positive and finite, else take the filter's alt.
 template <typename T>
 __global__ void __launch_bounds__(256)
-select_kernel(T *__restrict__ d, const T *__restrict__ alt, const double *__restrict__ rd, int64_t np, int B, int N,
-              int64_t total) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const int c = (int)(i / (np * B)) * B + (int)(i % B);
+select_kernel(T *__restrict__ d, const T *__restrict__ alt, const double *__restrict__ rd,
+              const int *__restrict__ use_net, int64_t np, int B, int N) {
+    // blockIdx.y: the block; B is a power of two
+    const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (il >= np * B) return;
+    const int64_t i = (int64_t)blockIdx.y * np * B + il;
+    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
     const double v = rd[N + c];
-    if (!(v > 0.0) || !isfinite(v)) d[i] = alt[i];
+    if (!use_net[c] || !(v > 0.0) || !isfinite(v)) d[i] = alt[i];
+}
+
+// The network is judged per state against its own record: a state whose
+// residual norm exceeds twice the smallest it has had takes the filter for
+// good.
+__global__ void net_reset_kernel(int N, int *__restrict__ use_net, double *__restrict__ best) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    use_net[c] = 1;
+    best[c] = INFINITY;
 }
 
 __global__ void active_kernel(const double *__restrict__ rr, int N, int B, double tol, int block_stop,
-                              double *__restrict__ res, int *__restrict__ active) {
+                              double *__restrict__ res, int *__restrict__ active, int judge,
+                              int *__restrict__ use_net, double *__restrict__ best) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
-    res[c] = sqrt(rr[c]);
+    const double r = sqrt(rr[c]);
+    res[c] = r;
     int act = 1;
     if (block_stop) {
         const int b0 = (c / B) * B;
@@ -352,6 +364,10 @@ __global__ void active_kernel(const double *__restrict__ rr, int N, int B, doubl
         for (int k = b0; k < b0 + B; ++k) act |= !(sqrt(rr[k]) < tol);
     }
     active[c] = act;
+    if (judge) {
+        if (!(r <= 2.0 * best[c])) use_net[c] = 0;
+        best[c] = fmin(best[c], r);
+    }
 }
 
 }  // namespace
@@ -369,8 +385,12 @@ struct rs_solver {
     rs::DevBuf R, d, hd, hpsi;
     rs::DevBuf partial, d2, d5, rr, res, eig, lam, eps, mats, coef, active;
     rs::DevBuf sigma, R0, rd;    // shifts, recorded residuals, <r|K r>
+    rs::DevBuf use_net, best;    // per state: network still used, smallest residual so far
     rs_cnn *cnn = nullptr;
+    bool net_reset = false;      // use_net / best start over at the next step
+    int rr_sweeps = kMaxSweeps;
     int steps = 0;
+    rs_solver_stats stats{};
 };
 
 extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc, int32_t nstates,
@@ -400,9 +420,15 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     o.tol = 1e-6;
     o.block_stop = 1;
     o.record = 0;
+    o.rr_sweeps = 0;
     if (opts) o = *opts;
     if (o.m < 1 || o.m > kMaxHist - 1) { delete s; return fail(RS_EINVAL, "rs_eigensolve_create: m must be 1..3"); }
+    if (o.rr_sweeps < 0 || o.rr_sweeps > kMaxSweeps) {
+        delete s;
+        return fail(RS_EINVAL, "rs_eigensolve_create: rr_sweeps must be 0..30");
+    }
     s->opts = o;
+    s->rr_sweeps = o.rr_sweeps ? o.rr_sweeps : kMaxSweeps;
     rs_status st = rs_ctx_create(g, s->N, &s->ctx);
     if (st) { delete s; return st; }
     const size_t es = dtype == RS_F64 ? 8 : 4;
@@ -429,6 +455,8 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (!st) st = s->active.alloc(sizeof(int) * N);
     if (!st) st = s->sigma.alloc(sizeof(double) * N);
     if (!st) st = s->rd.alloc(sizeof(double) * 2 * N);
+    if (!st) st = s->use_net.alloc(sizeof(int) * N);
+    if (!st) st = s->best.alloc(sizeof(double) * N);
     if (!st && o.record) st = s->R0.alloc(s->field_bytes);
     if (st) {
         rs_ctx_destroy(s->ctx);
@@ -460,9 +488,9 @@ rs_status precond(rs_solver *S, const T *r, T *d, T *alt, hipStream_t st) {
                           st)))
         return e;
     if ((e = filter_apply(g, S->opts.alpha, r, alt, S->nblk, S->B, S->dtype, st))) return e;
-    const int64_t total = g->np * S->N;
-    hipLaunchKernelGGL(select_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, d, alt,
-                       S->rd.as<double>(), g->np, S->B, S->N, total);
+    const dim3 gb((unsigned)((g->np * S->B + 255) / 256), S->nblk);
+    hipLaunchKernelGGL(select_kernel<T>, gb, dim3(256), 0, st, d, alt, S->rd.as<double>(), S->use_net.as<int>(),
+                       g->np, S->B, S->N);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -481,9 +509,14 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     rs_status e;
     // 1. H psi, Rayleigh-Ritz
     if ((e = hpsi_apply(g, S->nl, S->vloc, psi, h0, nblk, B, S->dtype, st))) return e;
-    if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, kSweeps,
+    if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, S->rr_sweeps,
                                   S->nreal, st)))
         return e;
+    if (S->cnn && S->net_reset) {
+        hipLaunchKernelGGL(net_reset_kernel, dim3(gs), dim3(64), 0, st, N, S->use_net.as<int>(),
+                           S->best.as<double>());
+        S->net_reset = false;
+    }
     // shifts for the learned preconditioner: sigma = -<psi|T psi>
     if (S->cnn || S->opts.record) {
         if ((e = kinetic_apply(g, psi, S->d.p, nblk, B, S->dtype, st))) return e;
@@ -498,7 +531,8 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
                           S->rr.as<double>(), st)))
         return e;
     hipLaunchKernelGGL(active_kernel, dim3(gs), dim3(64), 0, st, S->rr.as<double>(), N, B, S->opts.tol,
-                       S->opts.block_stop, S->res.as<double>(), S->active.as<int>());
+                       S->opts.block_stop, S->res.as<double>(), S->active.as<int>(), S->cnn ? 1 : 0,
+                       S->use_net.as<int>(), S->best.as<double>());
     if (S->opts.record) RS_HIP(hipMemcpyAsync(S->R0.p, S->R.p, S->field_bytes, hipMemcpyDeviceToDevice, st));
     // 3. trial step
     if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
@@ -586,9 +620,20 @@ extern "C" rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, do
     e = orthonormalize_impl(s->ctx, psi, s->nblk, s->B, s->dtype, s->prec, nullptr, &info, s->nreal, st);
     const int n = s->nreal;
     std::vector<double> ev(n), rn(n);
+    std::vector<int> act(s->N), net(s->N);
+    int sweeps = 0;
     RS_HIP(hipMemcpyAsync(ev.data(), s->eig.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     RS_HIP(hipMemcpyAsync(rn.data(), s->res.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    RS_HIP(hipMemcpyAsync(act.data(), s->active.p, sizeof(int) * s->N, hipMemcpyDeviceToHost, st));
+    RS_HIP(hipMemcpyAsync(&sweeps, ctx_sweeps(s->ctx), sizeof(int), hipMemcpyDeviceToHost, st));
+    if (s->cnn) RS_HIP(hipMemcpyAsync(net.data(), s->use_net.p, sizeof(int) * s->N, hipMemcpyDeviceToHost, st));
     RS_HIP(hipStreamSynchronize(st));
+    s->stats.rr_sweeps = sweeps;
+    s->stats.frozen_blocks = 0;
+    for (int b = 0; b < s->nblk; ++b) s->stats.frozen_blocks += act[(size_t)b * s->B] == 0;
+    s->stats.net_states = 0;
+    if (s->cnn)
+        for (int k = 0; k < n; ++k) s->stats.net_states += net[k] != 0;
     if (eig) std::memcpy(eig, ev.data(), sizeof(double) * n);
     if (resnorm) std::memcpy(resnorm, rn.data(), sizeof(double) * n);
     int c = 0;
@@ -598,12 +643,20 @@ extern "C" rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, do
         if (!std::isfinite(ev[k]) || !std::isfinite(rn[k]))
             return fail(RS_ENONFINITE, "rs_eigensolve_step: non-finite eigenvalue or residual");
     s->steps++;
+    s->stats.steps = s->steps;
     return e;
+}
+
+extern "C" rs_status rs_eigensolve_stats(const rs_solver *s, rs_solver_stats *out) {
+    if (!s || !out) return rs::fail(RS_EINVAL, "rs_eigensolve_stats: null argument");
+    *out = s->stats;
+    return RS_OK;
 }
 
 extern "C" rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c) {
     if (!s) return rs::fail(RS_EINVAL, "rs_eigensolve_set_precond: null solver");
     s->cnn = c;
+    s->net_reset = c != nullptr;
     return RS_OK;
 }
 

@@ -46,9 +46,9 @@ def test_one_step_matches_oracle(m):
     t = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
     eig, res, nconv = solver.step(t)
     got = rsd.from_blocks(t.cpu().numpy())
-    assert np.max(np.abs(eig - want["eig"])) < 1e-10 * np.max(np.abs(want["eig"]))
-    assert np.max(np.abs(res - want["resnorm"])) < 1e-8 * np.max(want["resnorm"])
-    assert np.max(np.abs(got - want["psi"])) < 1e-7 * np.max(np.abs(want["psi"]))
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-10 * np.max(np.abs(want["psi"]))
 
 
 def test_block_stop_freezes_converged_blocks():
@@ -113,9 +113,9 @@ def test_partial_last_block_step_matches_oracle():
     full = rsd.from_blocks(t.cpu().numpy())
     assert np.all(full[N:] == 0.0)
     got = full[:N]
-    assert np.max(np.abs(eig - want["eig"])) < 1e-10 * np.max(np.abs(want["eig"]))
-    assert np.max(np.abs(res - want["resnorm"])) < 1e-8 * np.max(want["resnorm"])
-    assert np.max(np.abs(got - want["psi"])) < 1e-7 * np.max(np.abs(want["psi"]))
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-10 * np.max(np.abs(want["psi"]))
 
 
 @pytest.mark.parametrize("dtype,etol", [(np.float64, 1e-10), (np.float32, 1e-6)])
@@ -166,3 +166,144 @@ def test_bad_solver_arguments_raise():
         with pytest.raises(rsd.RsError) as e:
             rsd.Eigensolver(g, None, v, n, B)
         assert e.value.code == rsd._abi.RS_EINVAL
+
+
+# ------------------------------------------------- the benchmark's shape
+# 128 states in blocks of 32 on a 113k-point sphere: the persistent
+# rotations at N = 128 (eight 16-state column blocks, X resident in LDS), and
+# the N = 128 LDS Cholesky, triangular inverse and Jacobi, as in the
+# benchmark's eigensolver runs.
+@pytest.fixture(scope="module")
+def bench_shape():
+    from oracle import cpu_hpsi
+    cpu_hpsi.build()
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=6.0, nat=6, atom_radius=4.0)
+    og, atoms, H = hamiltonian.build_system(w)
+    F = cpu_hpsi.FastHamiltonian(H)
+    psi0, _, _ = linalg.orthonormalize(synthetic.draw_states(synthetic.rng_after_atoms(w), 128, og.np), og.dv)
+    opts = rmmdiis.Options(m=3, block=32, tol=1e-12)
+    first = rmmdiis.rmmdiis_step(F, psi0, opts)      # the step from the random start
+    psi = first["psi"]
+    for _ in range(4):                                # oracle state after 5 steps
+        psi = rmmdiis.rmmdiis_step(F, psi, opts)["psi"]
+    after5 = rmmdiis.rmmdiis_step(F, psi, opts)
+    return dict(w=w, og=og, atoms=atoms, H=H, psi0=psi0, first=first, psi5=psi, after5=after5)
+
+
+def _bench_solver(S, dtype):
+    w, og, atoms = S["w"], S["og"], S["atoms"]
+    g = rsd.Grid.for_workload(w)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=128)
+    v = torch.from_numpy(S["H"].vloc.astype(dtype)).to(DEV)
+    return g, nl, v, rsd.Eigensolver(g, nl, v, 128, 32, m=3, tol=1e-12)
+
+
+def test_step_bench_shape_fp64_random_start(bench_shape):
+    """From random orthonormal states the subspace matrix is dense: the
+    Jacobi eigensolver runs to FP64 convergence (more than the 6 sweeps an
+    earlier version capped it at) and the step matches the oracle's, whose
+    Rayleigh-Ritz uses LAPACK."""
+    S = bench_shape
+    g, nl, v, solver = _bench_solver(S, np.float64)
+    want = S["first"]
+    t = torch.from_numpy(rsd.to_blocks(S["psi0"], 32)).to(DEV)
+    eig, res, _ = solver.step(t)
+    st = solver.stats()
+    print(f"rr_sweeps {st['rr_sweeps']}")
+    assert st["rr_sweeps"] > 6
+    got = rsd.from_blocks(t.cpu().numpy())
+    print(f"eig {np.max(np.abs(eig - want['eig']) / np.abs(want['eig'])):.2e} "
+          f"res {np.max(np.abs(res - want['resnorm']) / want['resnorm']):.2e} "
+          f"psi {np.max(np.abs(got - want['psi'])) / np.max(np.abs(want['psi'])):.2e}")
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-10 * np.max(np.abs(want["psi"]))
+
+
+def test_step_bench_shape_fp64(bench_shape):
+    """One FP64 step from the oracle's state after 5 steps."""
+    S = bench_shape
+    g, nl, v, solver = _bench_solver(S, np.float64)
+    want = S["after5"]
+    t = torch.from_numpy(rsd.to_blocks(S["psi5"], 32)).to(DEV)
+    eig, res, _ = solver.step(t)
+    got = rsd.from_blocks(t.cpu().numpy())
+    print(f"rr_sweeps {solver.stats()['rr_sweeps']} eig {np.max(np.abs(eig - want['eig'])):.2e} Ha "
+          f"res {np.max(np.abs(res - want['resnorm']) / want['resnorm']):.2e} "
+          f"psi {np.max(np.abs(got - want['psi'])) / np.max(np.abs(want['psi'])):.2e}")
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-10 * np.max(np.abs(want["psi"]))
+
+
+def test_step_bench_shape_split_precision(bench_shape):
+    """The precision form (FP32 fields, split-BF16 contractions, FP64 small
+    matrices): H psi of the oracle's 5-step state and one step from it,
+    against the FP64 oracle; errors per H psi and per eigenvalue."""
+    S = bench_shape
+    g, nl, v, solver = _bench_solver(S, np.float32)
+    x32 = S["psi5"].astype(np.float32)
+    t = torch.from_numpy(rsd.to_blocks(x32, 32)).to(DEV)
+    th = torch.empty_like(t)
+    rsd.hpsi_block(g, nl, v, t, th)
+    hp = rsd.from_blocks(th.cpu().numpy()).astype(np.float64)
+    want_h = S["H"].apply(x32.astype(np.float64))
+    herr = np.max(np.abs(hp - want_h), axis=1) / np.max(np.abs(want_h), axis=1)
+    want = S["after5"]
+    eig, res, _ = solver.step(t)
+    got = rsd.from_blocks(t.cpu().numpy()).astype(np.float64)
+    eerr = np.abs(eig - want["eig"])
+    perr = np.max(np.abs(got - want["psi"])) / np.max(np.abs(want["psi"]))
+    print(f"H psi max rel err per state {herr.max():.2e}; eigenvalue err max {eerr.max():.2e} Ha "
+          f"median {np.median(eerr):.2e}; psi {perr:.2e}")
+    assert herr.max() < 1e-5
+    assert eerr.max() < 2e-6
+    assert np.max(np.abs(res - want["resnorm"]) / want["resnorm"]) < 1e-3
+    assert perr < 1e-4
+
+
+def _harmonic_1d(n=32, h=0.3):
+    """Eigenpairs of the 1-D factor of the harmonic box (25-point star =
+    sum of three 1-D 9-point operators; Dirichlet, cell-centred)."""
+    from oracle import stencil
+    c = stencil.fd_weights(4)
+    x = (np.arange(n) - 0.5 * (n - 1)) * h
+    T = np.zeros((n, n))
+    for i in range(n):
+        T[i, i] = c[0]
+        for m in range(1, 5):
+            for j in (i - m, i + m):
+                if 0 <= j < n:
+                    T[i, j] = c[m]
+    A = -0.5 / h ** 2 * T + np.diag(0.5 * x * x)
+    return np.linalg.eigh(A)
+
+
+def test_converges_harmonic_box_eight_states():
+    """Config 1 as stated: 8 states, so state 8 is one member of the
+    degenerate triplet at 3.4999938080 Ha.  Eigenvalues reach the exact
+    separable spectrum; the spectral projector of the first triplet matches
+    the exact one built from the 1-D eigenvectors (eigenvectors of a
+    degenerate cluster are compared only through their projector)."""
+    w = synthetic.make_workload("box32_harmonic", nstates=8)
+    og, H, g, solver, psi = _setup(w, 8, 8, tol=1e-9)
+    t = torch.from_numpy(rsd.to_blocks(psi, 8)).to(DEV)
+    want = np.array([1.4999991750] + [2.4999964915] * 3 + [3.4999835553] * 3 + [3.4999938080])
+    for it in range(300):
+        eig, res, nconv = solver.step(t)
+        if nconv == 8:
+            break
+    print(f"steps {it + 1}, max res {res.max():.2e}")
+    assert np.max(np.abs(eig - want)) < 1e-9
+    e1, u1 = _harmonic_1d()
+    ix = og.inner[:, 0] - og.inner[:, 0].min()
+    iy = og.inner[:, 1] - og.inner[:, 1].min()
+    iz = og.inner[:, 2] - og.inner[:, 2].min()
+    trip = np.stack([u1[ix, a] * u1[iy, b] * u1[iz, c] for a, b, c in ((1, 0, 0), (0, 1, 0), (0, 0, 1))])
+    trip /= og.dv ** 0.5
+    got = rsd.from_blocks(t.cpu().numpy())[1:4]
+    # projectors compared through their action on a fixed set of vectors
+    probe = np.random.default_rng(0).normal(size=(5, og.np))
+    Pg = og.dv * (probe @ got.T) @ got
+    Pe = og.dv * (probe @ trip.T) @ trip
+    assert np.max(np.abs(Pg - Pe)) < 1e-6 * np.max(np.abs(Pe))
