@@ -11,8 +11,8 @@
 #include <algorithm>
 #include <cmath>
 
-#include "internal.hpp"
 #include "dense.hpp"
+#include "internal.hpp"
 
 namespace rs {
 namespace {
@@ -253,7 +253,7 @@ gram_bf16x3_kernel(const float *__restrict__ X, const float *__restrict__ Y, int
 // (consecutive threads read consecutive entries of one chunk); pass 2: one
 // thread per output entry sums the groups in order, mirrors (SYRK, mode 1)
 // or symmetrises (mode 2), and scales by dv.
-constexpr int kRedGroups = 16;
+constexpr int kRedGroups = kGramRedGroups;
 __global__ void __launch_bounds__(256)
 gram_reduce1_kernel(const double *__restrict__ partial, int nchunks, int cpg, int64_t ne,
                     double *__restrict__ red) {
@@ -365,12 +365,7 @@ rotate_f64_lds_kernel(double *__restrict__ psi, const double *__restrict__ Xm, i
 // 4j + i from every group and the X rows in the same order, which sums the
 // same 16 products.  Two register buffers alternate so that the next
 // block's loads are in flight while the current one is multiplied.
-#ifndef RS_ROT_VEC
-#define RS_ROT_VEC 1
-#endif
-#ifndef RS_ROT_MT
-#define RS_ROT_MT 2          // 16-point row blocks per wave in the persistent rotation
-#endif
+constexpr int kRotMT = 2;    // 16-point row blocks per wave in the persistent rotation
 template <int MT, int MAXC>
 __global__ void __launch_bounds__(512)
 rotate_f64_vec_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N,
@@ -1091,41 +1086,51 @@ __global__ void expand_kernel(const double *__restrict__ Vc, int n, int N, doubl
 
 }  // namespace
 
+// 16 x 16 output blocks of an N16 x N16 product: all of them (full), and
+// those with row block <= column block in row order (symmetric product).
+__global__ void gram_blocks_kernel(int nb16, int2 *__restrict__ full, int2 *__restrict__ syrk) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nb16 * nb16) return;
+    const int i = t / nb16, j = t % nb16;
+    full[t] = int2{i, j};
+    if (i <= j) syrk[i * nb16 - i * (i - 1) / 2 + (j - i)] = int2{i, j};
+}
+
 // ------------------------------------------------------------ launchers
 rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, int nblk, int dtype,
                int prec, double dv, double *S, int mode, hipStream_t st) {
+    const int N16 = (nblk * B + 15) / 16 * 16;
+    GramScratch ws{w.partial.as<double>(), (int64_t)w.partial.bytes, w.red.as<double>(), w.d_blocks_full.as<int2>(),
+                   w.d_blocks_syrk.as<int2>(), w.max_chunks};
+    rs_status e = gram_core(ws, w.blocks_n != N16, X, Y, np, B, nblk, dtype, prec, dv, S, mode, st);
+    if (!e) w.blocks_n = N16;
+    return e;
+}
+
+rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const void *Y, int64_t np, int B,
+                    int nblk, int dtype, int prec, double dv, double *S, int mode, hipStream_t st) {
     const int N = nblk * B;
     const int N16 = (N + 15) / 16 * 16;
     const bool syrk = X == Y;
     const int nb16 = N16 / 16;
-    // block list (row block <= col block for the symmetric product)
-    std::vector<int2> &bl = syrk ? w.blocks_syrk : w.blocks_full;
-    if ((int)bl.size() == 0 || w.blocks_n != N16) {
-        w.blocks_syrk.clear();
-        w.blocks_full.clear();
-        for (int i = 0; i < nb16; ++i)
-            for (int j = 0; j < nb16; ++j) {
-                w.blocks_full.push_back(int2{i, j});
-                if (i <= j) w.blocks_syrk.push_back(int2{i, j});
-            }
-        w.blocks_n = N16;
-        RS_HIP(hipMemcpyAsync(w.d_blocks_syrk.p, w.blocks_syrk.data(), w.blocks_syrk.size() * sizeof(int2),
-                              hipMemcpyHostToDevice, st));
-        RS_HIP(hipMemcpyAsync(w.d_blocks_full.p, w.blocks_full.data(), w.blocks_full.size() * sizeof(int2),
-                              hipMemcpyHostToDevice, st));
+    if (make_lists) {
+        hipLaunchKernelGGL(gram_blocks_kernel, dim3((nb16 * nb16 + 255) / 256), dim3(256), 0, st, nb16,
+                           w.blocks_full, w.blocks_syrk);
+        RS_HIP(hipGetLastError());
     }
-    const int nblocks = (int)bl.size();
-    const int2 *dbl = syrk ? w.d_blocks_syrk.as<int2>() : w.d_blocks_full.as<int2>();
+    const int nblocks = syrk ? nb16 * (nb16 + 1) / 2 : nb16 * nb16;
+    const int2 *dbl = syrk ? w.blocks_syrk : w.blocks_full;
     const int per_wg = 4 * MAXB;
     const int nsplit = (nblocks + per_wg - 1) / per_wg;
     const int bps = (nblocks + nsplit - 1) / nsplit;
     const bool bf = dtype == RS_F32 && prec == RS_PREC_BF16X3;
     // small chunks: several work-groups per compute unit (each owns all
     // output blocks of its chunk), bounded by the partial-sum workspace
-    int CP = bf ? 1024 : 512;
+    int64_t CP = bf ? 1024 : 512;
     while ((np + CP - 1) / CP > w.max_chunks) CP *= 2;
+    if (CP > (1 << 30)) return fail(RS_EINVAL, "gram: grid too large for the partial-sum workspace");
     const int nchunks = (int)((np + CP - 1) / CP);
-    if ((int64_t)nchunks * N16 * N16 * (int64_t)sizeof(double) > (int64_t)w.partial.bytes)
+    if ((int64_t)nchunks * N16 * N16 * (int64_t)sizeof(double) > w.partial_bytes)
         return fail(RS_EINVAL, "gram: workspace too small");
     dim3 grid(nchunks, nsplit);
     if (dtype == RS_F64) {
@@ -1134,7 +1139,7 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
         const int nbw = (bps % 4 == 0 && nblocks % bps == 0) ? bps / 4 : 0;
 #define RS_GRAM64(S, NB)                                                                                  \
     hipLaunchKernelGGL((gram_f64_kernel<S, NB>), grid, dim3(256), lds, st, (const double *)X, (const double *)Y, \
-                       np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>())
+                       np, B, N, N16, (int)CP, dbl, nblocks, bps, w.partial)
         // (the interleaved form is faster at 9 blocks per wave, the symmetric
         // product of 128 states; at 16 its 128 accumulators cost occupancy)
         if (nbw == 9) {
@@ -1149,7 +1154,7 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
         const size_t lds = (syrk ? 2 : 4) * (size_t)N16 * LDSROW * sizeof(unsigned short);
 #define RS_GRAMBF(S, V)                                                                                   \
     hipLaunchKernelGGL((gram_bf16x3_kernel<S, V>), grid, dim3(256), lds, st, (const float *)X, (const float *)Y, \
-                       np, B, N, N16, CP, dbl, nblocks, bps, w.partial.as<double>())
+                       np, B, N, N16, (int)CP, dbl, nblocks, bps, w.partial)
         if (B % 4 == 0) {
             if (syrk) RS_GRAMBF(true, true);
             else RS_GRAMBF(false, true);
@@ -1168,9 +1173,9 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
         const int ng = std::min(kRedGroups, nchunks);
         const int cpg = (nchunks + ng - 1) / ng;
         hipLaunchKernelGGL(gram_reduce1_kernel, dim3((unsigned)((ne + 255) / 256), ng), dim3(256), 0, st,
-                           w.partial.as<double>(), nchunks, cpg, ne, w.red.as<double>());
+                           w.partial, nchunks, cpg, ne, w.red);
         RS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(gram_reduce2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, w.red.as<double>(), ng,
+        hipLaunchKernelGGL(gram_reduce2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, w.red, ng,
                            N, N16, rmode, dv, S);
     }
     RS_HIP(hipGetLastError());
@@ -1184,22 +1189,22 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
     const int ncb = N16 / 16;
     if (dtype == RS_F64) {
         const size_t lds = (size_t)KR * (ncb * 16 + 4) * sizeof(double);
-        if (RS_ROT_VEC && B % 16 == 0 && ncb <= 8) {
+        if (B % 16 == 0 && ncb <= 8) {
             // X resident in LDS, one persistent work-group per CU
             if (!w.rot_lds_set) {
-                RS_HIP(hipFuncSetAttribute((const void *)rotate_f64_px_kernel<RS_ROT_MT>,
+                RS_HIP(hipFuncSetAttribute((const void *)rotate_f64_px_kernel<kRotMT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, kRotXLds));
                 int dev = 0;
                 RS_HIP(hipGetDevice(&dev));
                 RS_HIP(hipDeviceGetAttribute(&w.ncu, hipDeviceAttributeMultiprocessorCount, dev));
                 w.rot_lds_set = true;
             }
-            const int64_t ntiles = (np + 128 * RS_ROT_MT - 1) / (128 * RS_ROT_MT);
+            const int64_t ntiles = (np + 128 * kRotMT - 1) / (128 * kRotMT);
             const size_t xl = (size_t)N16 * (N16 + kRotPad) * sizeof(double);
             const unsigned grid = (unsigned)std::min<int64_t>(ntiles, std::max(w.ncu, 1));
-            hipLaunchKernelGGL((rotate_f64_px_kernel<RS_ROT_MT>), dim3(grid), dim3(512), xl, st, (double *)psi, Xm, np,
+            hipLaunchKernelGGL((rotate_f64_px_kernel<kRotMT>), dim3(grid), dim3(512), xl, st, (double *)psi, Xm, np,
                                B, N, ncb, ntiles, skip);
-        } else if (RS_ROT_VEC && B % 16 == 0) {
+        } else if (B % 16 == 0) {
             // ncb > 8 here: the persistent kernel above takes the rest
             hipLaunchKernelGGL((rotate_f64_vec_kernel<1, MAXC64>), dim3((unsigned)((np + 127) / 128)), dim3(512),
                                lds, st, (double *)psi, Xm, np, B, N, ncb, skip);
@@ -1218,7 +1223,7 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
                            w.xth.as<unsigned short>(), w.xtl.as<unsigned short>(), w.xtm.as<unsigned short>());
         RS_HIP(hipGetLastError());
         const size_t lds = (size_t)3 * ncb * 16 * XLD * sizeof(unsigned short);
-        if (RS_ROT_VEC && B % 8 == 0 && ncb <= 8 && N32 <= 128) {
+        if (B % 8 == 0 && ncb <= 8 && N32 <= 128) {
             // all slices of X resident in LDS, one persistent work-group per CU
             if (!w.rotbf_lds_set) {
                 RS_HIP(hipFuncSetAttribute((const void *)rotate_bf16x3_px_kernel<2>,
@@ -1354,3 +1359,4 @@ rs_status eigh_leading(DenseWork &w, double *A, double *V, double *evals, int N,
 }
 
 }  // namespace rs
+

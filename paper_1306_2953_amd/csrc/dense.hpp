@@ -14,8 +14,7 @@ struct DenseWork {
     int max_chunks = 512;               // set by dense_work_init
     DevBuf partial;                    // double [max_chunks][N16][N16]
     DevBuf red;                        // double [16][N16][N16] group sums of the partials
-    std::vector<int2> blocks_syrk, blocks_full;
-    int blocks_n = 0;
+    int blocks_n = 0;                  // N16 the block lists were built for
     DevBuf d_blocks_syrk, d_blocks_full;
     DevBuf mwork;                      // double [N][N] scratch
     DevBuf xth, xtm, xtl;              // bfloat16 [N16][N32] three-term split rotation matrix
@@ -27,6 +26,20 @@ struct DenseWork {
 };
 
 rs_status dense_work_init(DenseWork &w, int64_t np, int max_states);
+// Scratch of the point-summed products: chunk partials (partial_bytes),
+// group sums red [16][N16][N16], and the 16 x 16 output block lists
+// [(N16/16)^2] (full) and [(N16/16)(N16/16+1)/2] (symmetric).
+constexpr int kGramRedGroups = 16;   // group sums of the chunk partials
+struct GramScratch {
+    double *partial;
+    int64_t partial_bytes;
+    double *red;
+    int2 *blocks_full, *blocks_syrk;
+    int max_chunks;
+};
+// gram on explicit scratch; make_lists: (re)build the block lists first.
+rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const void *Y, int64_t np, int B,
+                    int nblk, int dtype, int prec, double dv, double *S, int mode, hipStream_t st);
 // S = dv X^T Y over points; mode 0 plain, 2 symmetrised (X == Y is computed
 // as a symmetric rank-k product).
 rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, int nblk, int dtype,

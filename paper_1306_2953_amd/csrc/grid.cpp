@@ -183,10 +183,7 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
         // a Morton curve inside each z layer of a pencil.  Bricks processed
         // together are then spatially compact and a brick's z neighbours are
         // processed just before and after it, while its neighbours are still
-        // in L2 (RS_EXEC_PENCIL 0: a plain 3-D Morton curve).
-#ifndef RS_EXEC_PENCIL
-#define RS_EXEC_PENCIL 1
-#endif
+        // in L2.
         auto spread = [](uint64_t v, int stride) {
             uint64_t m = 0;
             for (int bit = 0; bit < 21; ++bit) m |= ((v >> bit) & 1) << (stride * bit);
@@ -199,14 +196,9 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
                 for (int64_t bx = 0; bx < nbx; ++bx) {
                     const int32_t b = g->brick_map[(bz * nby + by) * nbx + bx];
                     if (b < 0) continue;
-                    uint64_t m;
-                    if (RS_EXEC_PENCIL) {
-                        const uint64_t tile = spread(bx >> 3, 2) | (spread(by >> 3, 2) << 1);
-                        const uint64_t inner = spread(bx & 7, 2) | (spread(by & 7, 2) << 1);
-                        m = (tile << 40) | ((uint64_t)bz << 8) | inner;
-                    } else {
-                        m = spread(bx, 3) | (spread(by, 3) << 1) | (spread(bz, 3) << 2);
-                    }
+                    const uint64_t tile = spread(bx >> 3, 2) | (spread(by >> 3, 2) << 1);
+                    const uint64_t inner = spread(bx & 7, 2) | (spread(by & 7, 2) << 1);
+                    const uint64_t m = (tile << 40) | ((uint64_t)bz << 8) | inner;
                     key.emplace_back(m, b);
                 }
         std::sort(key.begin(), key.end());
