@@ -197,6 +197,25 @@ void rs_ctx_destroy(rs_ctx *c);
 rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t nblk,
                      int32_t B, int32_t dtype, int32_t prec, void *stream);
 
+/* rs_overlap for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * product S = h^3 X^T Y (DEVICE double [N][N]) with no context.  Its chunk
+ * partial sums, group sums and block lists live in a fixed 64 MiB device
+ * array that the library holds on each GPU it runs on until the process
+ * ends; the call performs no allocation of any kind.  Limits: N = nblk*B in
+ * [1, 256] (else RS_EINVAL); the points per chunk grow past 4096 when the
+ * array holds fewer partial sums than the grid has 4096-point chunks (for
+ * 256 states, grids above about 450k points; for 128, above 2M), which
+ * changes only the rounding.  Every call on a GPU uses that GPU's one
+ * array, whose contents the last call leaves behind (nothing in it needs to
+ * start at zero): calls that overlap in time on one GPU (any streams, any
+ * threads) race and give wrong results.  The array's device address is
+ * looked up once per device, on the first call made with it current.
+ * Errors as rs_overlap.  Asynchronous. */
+rs_status rs_overlap_noalloc(const rs_grid *g, const void *x, const void *y, double *S,
+                             int32_t nblk, int32_t B, int32_t dtype, int32_t prec,
+                             void *stream);
+
 /* psi <- psi X in place (eqs. (8) and (10): new state c = sum_n X[n][c] old
  * state n); X is DEVICE double [N][N].  Asynchronous. */
 rs_status rs_rotate(rs_ctx *c, void *psi, const double *X, int32_t nblk, int32_t B,

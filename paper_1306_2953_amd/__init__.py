@@ -221,6 +221,23 @@ def apply_nl(grid: Grid, nl: NonLocal, proj, hpsi, stream=None):
     return hpsi
 
 
+def overlap_noalloc(grid: Grid, x, y, S, prec=None, stream=None):
+    """S [N, N] (float64, caller-allocated) = h^3 X^T Y with the library's
+    fixed device scratch (rs_overlap_noalloc): N <= 256, no allocation."""
+    torch = _torch()
+    nblk, B = _blocks(x, grid)
+    _check(y, "y", like=x)
+    N = nblk * B
+    if N > 256:
+        raise ValueError(f"rs_overlap_noalloc handles at most 256 states, got {N}")
+    _check(S, "S", shape=(N, N), dtype=torch.float64)
+    if S.device != x.device:
+        raise ValueError("S must be on x's device")
+    check(lib().rs_overlap_noalloc(grid.handle, _dev(x, "x"), _dev(y, "y"), _dev(S, "S"), nblk, B,
+                                   _dtype_code(x), Context._prec(x, prec), _stream(stream)))
+    return S
+
+
 class Context:
     """Workspaces of the orthogonalisation / subspace stage (rs_ctx)."""
 

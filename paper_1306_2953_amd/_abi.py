@@ -59,6 +59,7 @@ SIGNATURES = {
     "rs_ctx_create": (ctypes.c_int, [P, I32, ctypes.POINTER(P)]),
     "rs_ctx_destroy": (None, [P]),
     "rs_overlap": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P]),
+    "rs_overlap_noalloc": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P]),
     "rs_rotate": (ctypes.c_int, [P, P, P, I32, I32, I32, I32, P]),
     "rs_cholesky": (ctypes.c_int, [P, P, P, I32, P, P]),
     "rs_eigh": (ctypes.c_int, [P, P, P, P, I32, P]),

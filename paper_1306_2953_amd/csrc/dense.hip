@@ -1360,3 +1360,78 @@ rs_status eigh_leading(DenseWork &w, double *A, double *V, double *evals, int N,
 
 }  // namespace rs
 
+
+// ------------------------------------------------- overlap without allocation
+// rs_overlap_noalloc runs the same point-summed product as rs_overlap, with
+// its chunk partials, group sums and block lists in `scratch`, a fixed device
+// array that the code object holds on every GPU the library runs on, so the
+// call allocates nothing.  In host code `scratch` names a host-side stand-in:
+// its device address comes from hipGetSymbolAddress, once per device, and
+// only that address is handed to kernels.
+#include <mutex>
+
+namespace {
+
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;   // 64 MiB per GPU
+constexpr int kNoallocMaxStates = 256;
+constexpr size_t kNoallocListBytes = 4096;                   // both block lists
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+rs_status noalloc_scratch(unsigned char **out) {
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return rs::fail(RS_EINVAL, "rs_overlap_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return rs::hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return rs::fail(RS_EHIP, "rs_overlap_noalloc: no device address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = (unsigned char *)g_scratch_dev[dev];
+    return RS_OK;
+}
+
+}  // namespace
+
+extern "C" rs_status rs_overlap_noalloc(const rs_grid *g, const void *x, const void *y, double *S, int32_t nblk,
+                                        int32_t B, int32_t dtype, int32_t prec, void *stream) {
+    using rs::fail;
+    if (!g || !x || !y || !S) return fail(RS_EINVAL, "rs_overlap_noalloc: null argument");
+    if (g->host_only) return fail(RS_EINVAL, "rs_overlap_noalloc: host-only grid");
+    if (B < 1 || B > 64 || (B & (B - 1))) return fail(RS_EINVAL, "rs_overlap_noalloc: B must be a power of two in [1, 64]");
+    if (nblk < 1 || (int64_t)nblk * B > kNoallocMaxStates)
+        return fail(RS_EINVAL, "rs_overlap_noalloc: nblk*B must be in [1, 256] (the fixed scratch holds the partial "
+                               "sums of at most 256 states)");
+    if (dtype == RS_F64 && prec != RS_PREC_NATIVE)
+        return fail(RS_ENOTSUP, "rs_overlap_noalloc: FP64 fields use RS_PREC_NATIVE contractions");
+    if (dtype == RS_F32 && prec != RS_PREC_BF16X3)
+        return fail(RS_ENOTSUP, "rs_overlap_noalloc: FP32 fields use RS_PREC_BF16X3 contractions");
+    if (dtype != RS_F64 && dtype != RS_F32) return fail(RS_EINVAL, "rs_overlap_noalloc: bad dtype");
+    unsigned char *base = nullptr;
+    rs_status st = noalloc_scratch(&base);
+    if (st) return st;
+    const int64_t N16 = ((int64_t)nblk * B + 15) / 16 * 16;
+    const int64_t mat = N16 * N16 * (int64_t)sizeof(double);
+    const int64_t red_bytes = rs::kGramRedGroups * mat;
+    const int64_t part_off = (int64_t)kNoallocListBytes + red_bytes;
+    const int64_t part_bytes = (int64_t)kNoallocScratchBytes - part_off;
+    rs::GramScratch ws;
+    ws.blocks_full = (int2 *)base;
+    ws.blocks_syrk = (int2 *)(base + kNoallocListBytes / 2);
+    ws.red = (double *)(base + kNoallocListBytes);
+    ws.partial = (double *)(base + part_off);
+    ws.partial_bytes = part_bytes;
+    ws.max_chunks = (int)(part_bytes / mat);
+    const double dv = g->h * g->h * g->h;
+    // the block lists are rebuilt on every call: the previous call on this
+    // GPU may have had another N
+    return rs::gram_core(ws, true, x, y, g->np, B, nblk, dtype, prec, dv, S, 0, (hipStream_t)stream);
+}
