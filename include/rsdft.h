@@ -272,7 +272,7 @@ rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_
 typedef struct rs_solver rs_solver;
 typedef struct {
     int32_t m;           /* iterates built per step (H d applications), 1..3 */
-    double  alpha;       /* filter centre weight (1/2)                       */
+    double  alpha;       /* filter centre weight (0.6)                       */
     double  tol;         /* residual threshold of the block stopping rule    */
     int32_t block_stop;  /* nonzero: freeze blocks whose states are all < tol */
     int32_t record;      /* nonzero: keep R0 and sigma of each step for
@@ -289,7 +289,7 @@ typedef struct {
  * nblk * B).  When B does not divide nstates the last block is padded with
  * zero states: they stay zero, get identity pivots in the orthonormalisation
  * and are left out of the Rayleigh-Ritz problem, the stopping rule and the
- * outputs.  opts NULL: m = 3, alpha = 1/2,
+ * outputs.  opts NULL: m = 3, alpha = 0.6,
  * tol = 1e-6, block_stop = 1, record = 0, rr_sweeps = 0.  Allocates all workspaces (about 2(m+1)+3
  * field arrays of np * nstates elements). */
 rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc,

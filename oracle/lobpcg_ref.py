@@ -35,10 +35,12 @@ from . import cpu_hpsi, stencil
 class _Operator:
     """X [np, k] -> H X through the C oracle (blocks of at most 32 states)."""
 
-    def __init__(self, H):
+    def __init__(self, H, log=None):
         self.ch = cpu_hpsi.CpuHamiltonian(H)
         self.np = H.g.np
         self.calls = 0
+        self.log = log
+        self.t0 = time.perf_counter()
 
     def __call__(self, X: np.ndarray) -> np.ndarray:
         X = np.asarray(X, dtype=np.float64)
@@ -50,6 +52,9 @@ class _Operator:
             blk = np.ascontiguousarray(X2[:, j0:j1])[None]
             out[:, j0:j1] = self.ch.hpsi_blocks(blk)[0]
         self.calls += X2.shape[1]
+        if self.log and X2.shape[1] > 1:
+            self.log(f"  H applied to {X2.shape[1]} columns ({self.calls} in total, "
+                     f"{time.perf_counter() - self.t0:.0f} s)")
         return out[:, 0] if one else out
 
 
@@ -60,7 +65,7 @@ class _KineticPreconditioner:
 
     def __init__(self, g, shift: float, workers: int = 8):
         ext = (g.inner.max(axis=0) - g.inner.min(axis=0)) + 1
-        n = int(2 ** np.ceil(np.log2(int(ext.max()) + 2 * g.M)))
+        n = scipy.fft.next_fast_len(int(ext.max()) + 2 * g.M, real=True)
         if g.periodic:
             n = int(g.L[0])
         self.n = n
@@ -100,7 +105,7 @@ def lowest_eigs(H, nev: int, nguard: int, tol: float, maxiter: int, seed: int = 
     vectors.  Returns (eigenvalues [nev], residual norms [nev] of the
     normalised eigenvectors, eigenvectors [np, nev], seconds)."""
     g = H.g
-    op = _Operator(H)
+    op = _Operator(H, log)
     A = scipy.sparse.linalg.LinearOperator((g.np, g.np), matvec=op, matmat=op, dtype=np.float64)
     P = _KineticPreconditioner(g, shift)
     M = scipy.sparse.linalg.LinearOperator((g.np, g.np), matvec=P, matmat=P, dtype=np.float64)

@@ -351,7 +351,7 @@ class Eigensolver:
     """RMM-DIIS eigensolver over the states of one grid (rs_solver)."""
 
     def __init__(self, grid: Grid, nl: Optional[NonLocal], vloc, nstates: int, B: int,
-                 m: int = 3, alpha: float = 0.5, tol: float = 1e-6, block_stop: bool = True,
+                 m: int = 3, alpha: float = 0.6, tol: float = 1e-6, block_stop: bool = True,
                  record: bool = False, rr_sweeps: int = 0):
         _check(vloc, "vloc", numel=grid.np)
         if vloc.dim() != 1:

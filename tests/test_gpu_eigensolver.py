@@ -280,21 +280,25 @@ def _harmonic_1d(n=32, h=0.3):
 
 
 def test_converges_harmonic_box_eight_states():
-    """Config 1 as stated: 8 states, so state 8 is one member of the
-    degenerate triplet at 3.4999938080 Ha.  Eigenvalues reach the exact
-    separable spectrum; the spectral projector of the first triplet matches
-    the exact one built from the 1-D eigenvectors (eigenvectors of a
-    degenerate cluster are compared only through their projector)."""
-    w = synthetic.make_workload("box32_harmonic", nstates=8)
-    og, H, g, solver, psi = _setup(w, 8, 8, tol=1e-9)
+    """Config 1 as stated: the lowest 8 states, so state 8 is one member of
+    the degenerate triplet at 3.4999938080 Ha, 1e-5 Ha above the triplet at
+    3.4999835553.  The solve carries 8 buffer states (16 in blocks of 8): with
+    exactly 8 the cut falls inside that 6-state cluster and the lower triplet
+    separates from the upper one at a rate set by their 1e-5 Ha gap.  The
+    lowest 8 eigenvalues reach the exact separable spectrum; the spectral
+    projector of the first triplet matches the exact one built from the 1-D
+    eigenvectors (eigenvectors of a degenerate cluster are compared only
+    through their projector)."""
+    w = synthetic.make_workload("box32_harmonic", nstates=16)
+    og, H, g, solver, psi = _setup(w, 16, 8, tol=1e-9)
     t = torch.from_numpy(rsd.to_blocks(psi, 8)).to(DEV)
     want = np.array([1.4999991750] + [2.4999964915] * 3 + [3.4999835553] * 3 + [3.4999938080])
     for it in range(300):
         eig, res, nconv = solver.step(t)
-        if nconv == 8:
+        if res[:8].max() < 1e-9:
             break
-    print(f"steps {it + 1}, max res {res.max():.2e}")
-    assert np.max(np.abs(eig - want)) < 1e-9
+    print(f"steps {it + 1}, max res of the lowest 8 {res[:8].max():.2e}")
+    assert np.max(np.abs(eig[:8] - want)) < 1e-9
     e1, u1 = _harmonic_1d()
     ix = og.inner[:, 0] - og.inner[:, 0].min()
     iy = og.inner[:, 1] - og.inner[:, 1].min()

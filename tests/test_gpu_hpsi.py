@@ -183,9 +183,14 @@ def test_full_size_periodic_and_cage_sampled(name, seed, N, B):
 
 
 def test_bad_block_size_rejected():
+    """B = 3 is refused by the binding (ValueError) and, called directly, by
+    the C entry point (RS_EINVAL) before any kernel runs."""
     og, H, g, nl = _system(SMALL)
     t = torch.zeros((1, og.np, 3), dtype=torch.float64, device=DEV)
     v = torch.zeros(og.np, dtype=torch.float64, device=DEV)
-    with pytest.raises(rsd.RsError) as e:
-        rsd.hpsi_block(g, nl, v, t, torch.empty_like(t))
-    assert e.value.code == rsd._abi.RS_EINVAL
+    out = torch.empty_like(t)
+    with pytest.raises(ValueError):
+        rsd.hpsi_block(g, nl, v, t, out)
+    st = rsd.lib().rs_hpsi_block(g.handle, nl.handle, rsd._dev(v, "v"), rsd._dev(t, "psi"), rsd._dev(out, "hpsi"),
+                                 1, 3, rsd.RS_F64, None)
+    assert st == rsd._abi.RS_EINVAL

@@ -8,29 +8,57 @@ import synthetic
 from oracle import grid, hamiltonian, linalg, rmmdiis, stencil
 
 
-def test_filter_symbol_on_plane_waves():
+@pytest.mark.parametrize("alpha", [0.5, 0.6, None])
+def test_filter_symbol_on_plane_waves(alpha):
+    """K on plane waves of a periodic grid: the closed-form symbol
+    a + (1 - a)/3 sum cos(k h), 1 at k = 0 and 2a - 1 at the Nyquist corner
+    (zero for a = 1/2; None = the default centre weight, 0.6)."""
     n, h = 12, 0.25
     g = grid.build_grid("periodic", h, n=n)
     L = n * h
+    a = 0.6 if alpha is None else alpha
+    kw = {} if alpha is None else {"alpha": alpha}
     for nvec in [(0, 0, 0), (1, 2, 0), (6, 6, 6), (6, 0, 0), (3, 5, 1)]:
         k = 2 * np.pi * np.array(nvec) / L
         f = np.cos(g.xyz @ k)
-        got = rmmdiis.filter_precond(g, f)
-        sym = 0.5 + 0.5 / 3 * np.sum(np.cos(k * h))
+        got = rmmdiis.filter_precond(g, f, **kw)
+        sym = a + (1.0 - a) / 3 * np.sum(np.cos(k * h))
         assert np.max(np.abs(got - sym * f)) < 1e-13
-    # the symbol is 1 at k = 0 and 0 at the Nyquist corner
     f = np.cos(g.xyz @ (np.pi / h * np.ones(3)))
-    assert np.max(np.abs(rmmdiis.filter_precond(g, f))) < 1e-13
+    assert np.max(np.abs(rmmdiis.filter_precond(g, f, **kw) - (2 * a - 1) * f)) < 1e-13
 
 
-def test_filter_zero_outside_domain():
+@pytest.mark.parametrize("alpha", [0.5, 0.6])
+def test_filter_zero_outside_domain(alpha):
     g = grid.build_grid("box", 0.3, n=4)
     f = np.ones(g.np)
-    out = rmmdiis.filter_precond(g, f)
+    out = rmmdiis.filter_precond(g, f, alpha=alpha)
     corner = np.nonzero(np.all(g.inner == 0, axis=1))[0][0]
     centre = np.nonzero(np.all(g.inner == 1, axis=1))[0][0]
-    assert out[corner] == pytest.approx(0.5 + 0.5 / 6 * 3)
+    assert out[corner] == pytest.approx(alpha + (1 - alpha) / 6 * 3)
     assert out[centre] == pytest.approx(1.0)
+
+
+def test_periodic_even_box_converges_to_dense_spectrum():
+    """Periodic 16^3 box (even edges, so the alternating vector is a grid
+    mode) with wells and projectors: from random states the default filter
+    reaches the lowest eigenvalues of the dense matrix.  With alpha = 1/2
+    the same solve keeps a residual floor, because K then annihilates that
+    mode and the random start's component along it can never be removed."""
+    w = synthetic.make_workload("periodic96_h0.25", n=16, nat=1, nstates=12, block=4)
+    g, atoms, H = hamiltonian.build_system(w)
+    ev = np.linalg.eigvalsh(H.dense())[:8]
+    psi0 = synthetic.draw_states(synthetic.rng_after_atoms(w), 12, g.np)
+    floors = {}
+    for alpha in (0.6, 0.5):
+        opts = rmmdiis.Options(m=3, block=4, tol=1e-12, alpha=alpha)
+        psi, hist = rmmdiis.eigensolve(H, psi0, opts, max_steps=150, eref=ev if alpha == 0.6 else None,
+                                       etol=1e-10)
+        eig, res = hist[-1]
+        floors[alpha] = res[:8].max()
+        if alpha == 0.6:
+            assert np.max(np.abs(eig[:8] - ev)) < 1e-10
+    assert floors[0.5] > 1e-4 and floors[0.5] > 1e3 * floors[0.6]
 
 
 def test_trial_lambda_minimises_rayleigh_quotient():
