@@ -61,7 +61,7 @@ def setup(w, dtype, B):
     del psi
     thpsi = torch.empty_like(tpsi)
     tv = torch.from_numpy(v.astype(npdt)).to(dev)
-    nblk = w.nstates // B
+    nblk = int(tpsi.shape[0])        # the last block padded with zero states when B does not divide N
     proj = None
     if nl is not None:
         proj = torch.empty((nblk, nl.nat, 4, B), dtype=tpsi.dtype, device=dev)
@@ -120,14 +120,19 @@ def run_gpu(w, dtype, B, steps, warmup):
 
 
 def cpu_baseline(w, budget_s=15.0):
-    """The FP64 C/OpenMP oracle on one block of B states of the workload,
-    repeated for about budget_s seconds."""
+    """The FP64 C/OpenMP oracle applying H to all the workload's seeded
+    states (every block), repeated for about budget_s seconds."""
     from oracle import cpu_hpsi, hamiltonian
+    cpu_hpsi.build()
     og, atoms, H = hamiltonian.build_system(w)
     ch = cpu_hpsi.CpuHamiltonian(H)
     B = w.block
-    rng = np.random.default_rng(0)
-    blk = rng.uniform(-1, 1, size=(1, og.np, B))
+    nblk = -(-w.nstates // B)
+    psi = synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, og.np)
+    blk = np.zeros((nblk, og.np, B))
+    for k in range(w.nstates):
+        blk[k // B, :, k % B] = psi[k]
+    del psi
     ch.hpsi_blocks(blk)                      # warm-up
     reps, t0 = 0, time.perf_counter()
     while True:
@@ -136,11 +141,10 @@ def cpu_baseline(w, budget_s=15.0):
         el = time.perf_counter() - t0
         if el > budget_s:
             break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=og.np * B * reps / el, unit="grid-pt*states/s", cores=threads,
-                kind="oracle",
-                sample=f"{reps} applications of FP64 H (stencil+V+KB) to one block of {B} "
-                       f"states on the {og.np}-point grid, {el:.1f} s")
+    return dict(value=og.np * w.nstates * reps / el, unit="grid-pt*states/s", cores=cpu_hpsi.threads(),
+                kind="oracle", cpu=cpu_hpsi.cpu_model(),
+                sample=f"{reps} applications of FP64 H (stencil+V+KB) to all {w.nstates} seeded states "
+                       f"({nblk} blocks of {B}) on the {og.np}-point grid, {el:.1f} s")
 
 
 def traffic_probe(w, dtype, B):
@@ -231,7 +235,17 @@ def measured_traffic(workload: str, dtype: str):
     return e.get("bytes_per_launch")
 
 
-def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every=20):
+def golden_eigs(name: str):
+    """Lowest eigenvalues of the workload's FP64 H from tests/golden (an
+    independent LOBPCG solve on the oracle's operator), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_eigs.txt")
+    if not os.path.exists(path):
+        return None, path
+    vals = [float(line.split()[1]) for line in open(path) if line.strip() and not line.startswith("#")]
+    return np.array(vals), path
+
+
+def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every=20, stop_at_hit=False):
     """Steps from the seeded start until the lowest N - nbuf states all have
     residual < tol_res (or max_steps).  Returns per-step wall times, the
     eigenvalue history and the time to |eps - ref| < 1e-6 on those states."""
@@ -264,24 +278,36 @@ def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every
         if log_every and k % log_every == 0:
             log(f"  {w.name} {dtype} step {k}: max res {res[:keep].max():.2e} eig0 {eig[0]:.10f} "
                 f"t {elapsed:.2f} s")
-        if np.all(res[:keep] < tol_res):
+        if np.all(res[:keep] < tol_res) or (stop_at_hit and t_hit is not None):
             break
     step_ms = 1e3 * (times[-1] - times[min(4, len(times) - 1)]) / max(1, len(times) - 1 - min(4, len(times) - 1))
     del solver, ctx, tp
     torch.cuda.empty_cache()
     return dict(steps=len(times), eig=eigs[-1], eigs=eigs, times=times, t_hit=t_hit, k_hit=k_hit,
-                ms_per_step=step_ms, keep=keep)
+                ms_per_step=step_ms, keep=keep, final_max_res=float(res[:keep].max()))
 
 
 def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
-    """FP32 solve of the periodic workload with the trained network against
-    the same solve with the filter, from the same seeded start.  The network
-    is trained first on the GPU (30 recorded filter steps, CG targets,
-    energy-norm loss).  Reference eigenvalues: the end of whichever run
-    reaches the smaller residual on the lowest N - nbuf states."""
+    """FP32 solve of the periodic workload with the trained network (a
+    second direction next to the filter's in every trial step) against the
+    same solve with the filter alone, from the same seeded start.  The
+    network is trained first on the GPU (30 recorded filter steps, CG
+    targets, energy-norm loss).  Reference eigenvalues: the golden LOBPCG
+    values when present, else an FP64 filter solve run to residual 1e-6 on
+    the lowest N - nbuf states."""
     import torch
     import paper_1306_2953_amd as rsd
     from paper_1306_2953_amd import learned
+    keep = w.nstates - nbuf
+    ref, path = golden_eigs(w.name)
+    if ref is not None and len(ref) >= keep:
+        refname = f"tests/golden/{os.path.basename(path)} (scipy LOBPCG on the oracle's FP64 operator)"
+    else:
+        log("learned compare: FP64 filter reference run")
+        r64 = eigensolve_run(w, "f64", w.block, 400, 1e-6, nbuf=nbuf)
+        ref = r64["eig"]
+        refname = (f"FP64 filter solve to residual {r64['final_max_res']:.1e} on those states "
+                   f"({r64['steps']} steps, {r64['ms_per_step']:.1f} ms per step)")
     g = rsd.Grid.for_workload(w)
     atoms = synthetic.draw_atoms(w)
     v = synthetic.potential_for(w, g.xyz(), atoms)
@@ -290,7 +316,6 @@ def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
     psi0 = torch.from_numpy(rsd.to_blocks(
         synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np).astype(np.float32), w.block)).cuda()
     rsd.Context(g, w.nstates).orthonormalize(psi0)
-    keep = w.nstates - nbuf
     box = int(np.prod([g.nb[a] * 4 for a in range(3)]))
     net = rsd.Cnn(max(32, w.block), max(box, 16 ** 3))
     net.set_params(learned.init_params(0))
@@ -313,74 +338,101 @@ def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
     npairs = pairs.n
     del pairs, tr, val
     torch.cuda.empty_cache()
-    runs = {}
+    out = {"workload": w.name, "states": w.nstates, "measured_states": keep, "reference": refname,
+           "metric": "steps and time to |eps - eps_ref| < 1e-6 Ha on the measured states",
+           "training": {"pairs": npairs, "iterations": train_iters, "collect_s": t_collect,
+                        "train_s": t_train, "validation_energy_norm_loss": vloss}}
     for name, pre in (("filter", None), ("learned", net)):
         s = rsd.Eigensolver(g, nl, tv, w.nstates, w.block, tol=1e-6)
         if pre is not None:
             s.set_precond(pre)
         x = psi0.clone()
-        el, times, eigs, maxres = 0.0, [], [], []
+        el, hit, nets = 0.0, None, []
         for k in range(max_steps):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             eig, res, _ = s.step(x)
             el += time.perf_counter() - t1
-            times.append(el)
-            eigs.append(eig.copy())
-            maxres.append(float(res[:keep].max()))
-            last_res = res[:keep].copy()
+            nets.append(s.stats()["net_states"])
+            err = float(np.max(np.abs(eig[:keep] - ref[:keep])))
             if k % 20 == 0:
-                log(f"  learned compare {name} step {k}: max res {maxres[-1]:.2e} t {el:.2f} s")
-            if maxres[-1] < 1e-5:
+                log(f"  learned compare {name} step {k}: max res {res[:keep].max():.2e} eig err {err:.1e} "
+                    f"t {el:.2f} s")
+            if err < 1e-6:
+                hit = (k + 1, el)
                 break
-        runs[name] = dict(times=times, eigs=eigs, maxres=maxres, last_res=last_res)
+        out[name] = {"steps_run": k + 1, "final_max_residual": float(res[:keep].max()),
+                     "final_median_residual": float(np.median(res[:keep])),
+                     "final_max_eig_error_ha": err, "ms_per_step": 1e3 * el / (k + 1),
+                     "steps_to_1e-6": None if hit is None else hit[0],
+                     "time_to_1e-6_s": None if hit is None else hit[1]}
+        if pre is not None:
+            out[name]["mean_states_using_network"] = float(np.mean(nets))
         del s, x
         torch.cuda.empty_cache()
-    best = min(runs, key=lambda n: runs[n]["maxres"][-1])
-    ref_res = runs[best]["maxres"][-1]
-    ref = runs[best]["eigs"][-1] if ref_res < 1e-5 else None   # eigenvalue error ~ residual^2
-    out = {"workload": w.name, "states": w.nstates, "measured_states": keep,
-           "reference": (f"final eigenvalues of the {best} run (max residual {ref_res:.1e})" if ref is not None
-                         else f"none: neither run reached residual 1e-5 (best {best}, {ref_res:.1e})"),
-           "training": {"pairs": npairs, "iterations": train_iters, "collect_s": t_collect,
-                        "train_s": t_train, "validation_energy_norm_loss": vloss}}
-    for name, r in runs.items():
-        hit = None
-        if ref is not None:
-            hit = next((k for k, e in enumerate(r["eigs"]) if np.max(np.abs(e[:keep] - ref[:keep])) < 1e-6), None)
-        out[name] = {"steps_run": len(r["times"]), "final_max_residual": r["maxres"][-1],
-                     "final_median_residual": float(np.median(r["last_res"])),
-                     "lowest_eigenvalue": float(r["eigs"][-1][0]),
-                     "ms_per_step": 1e3 * r["times"][-1] / len(r["times"]),
-                     "time_to_1e-6_s": None if hit is None else r["times"][hit],
-                     "steps_to_1e-6": None if hit is None else hit + 1}
     return out
 
 
-def eigensolve_compare(max_steps=600):
-    """Plain FP64 filter solve on the 128-state sphere (its converged end is
-    the reference) against the FP32 split-precision solve of the same system."""
+def eigensolve_compare(max_steps=400):
+    """Plain FP64 filter solve of the 128-state sphere and the FP32
+    split-precision solve of the same system, each timed until its lowest
+    N - 16 eigenvalues are within 1e-6 Ha of the reference: the golden
+    LOBPCG eigenvalues when present, else the FP64 run's converged end."""
     w2, w3 = synthetic.WORKLOADS["sphere_r12_h0.2"], synthetic.WORKLOADS["sphere_r12_h0.2_fp32"]
-    log("eigensolve: FP64 reference / plain run")
-    r64 = eigensolve_run(w2, "f64", w2.block, max_steps, 1e-6)
-    ref = r64["eig"]
-    keep = r64["keep"]
-    t_hit = k_hit = None
-    for k, (t, e) in enumerate(zip(r64["times"], r64["eigs"])):
-        if np.max(np.abs(e[:keep] - ref[:keep])) < 1e-6:
-            t_hit, k_hit = t, k + 1
-            break
+    ref, path = golden_eigs(w2.name)
+    keep = w2.nstates - 16
+    if ref is not None and len(ref) >= keep:
+        log("eigensolve: FP64 plain run against the golden eigenvalues")
+        r64 = eigensolve_run(w2, "f64", w2.block, max_steps, 1e-6, ref=ref, stop_at_hit=True)
+        refname = f"tests/golden/{os.path.basename(path)} (scipy LOBPCG on the oracle's FP64 operator)"
+    else:
+        log("eigensolve: FP64 reference / plain run")
+        r64 = eigensolve_run(w2, "f64", w2.block, 600, 1e-6)
+        ref = r64["eig"]
+        for k, (t, e) in enumerate(zip(r64["times"], r64["eigs"])):
+            if np.max(np.abs(e[:keep] - ref[:keep])) < 1e-6:
+                r64["t_hit"], r64["k_hit"] = t, k + 1
+                break
+        refname = f"FP64 run converged to residual < 1e-6 on those states ({r64['steps']} steps)"
+    err64 = float(np.max(np.abs(r64["eig"][:keep] - ref[:keep])))
     log("eigensolve: FP32 split-precision run")
-    r32 = eigensolve_run(w3, "f32", w3.block, max_steps, 1e-5, ref=ref)
+    r32 = eigensolve_run(w3, "f32", w3.block, max_steps, 1e-5, ref=ref, stop_at_hit=True)
     err32 = float(np.max(np.abs(r32["eig"][:keep] - ref[:keep])))
     return {
         "metric": "time to |eps - eps_ref| < 1e-6 Ha on the lowest N-16 states",
-        "workload": w2.name, "states": w2.nstates, "measured_states": keep,
-        "reference": f"FP64 run converged to residual < 1e-6 on those states ({r64['steps']} steps)",
-        "plain_fp64_filter": {"time_s": t_hit, "steps": k_hit, "ms_per_step": r64["ms_per_step"]},
+        "workload": w2.name, "states": w2.nstates, "measured_states": keep, "reference": refname,
+        "plain_fp64_filter": {"time_s": r64["t_hit"], "steps": r64["k_hit"], "ms_per_step": r64["ms_per_step"],
+                              "final_max_eig_error_ha": err64, "final_max_residual": r64["final_max_res"]},
         "fp32_split_filter": {"time_s": r32["t_hit"], "steps": r32["k_hit"],
                               "ms_per_step": r32["ms_per_step"], "steps_run": r32["steps"],
-                              "final_max_eig_error_ha": err32},
+                              "final_max_eig_error_ha": err32, "final_max_residual": r32["final_max_res"]},
+    }
+
+
+def cage_compare(max_steps=300):
+    """The large sphere (4.19M points, 60-atom cage, 240 states in blocks of
+    64, the last padded): plain FP64 filter solve run to residual 1e-6 on the
+    lowest N - 16 states (its end is the reference: no independent solve of
+    this size exists), and the FP32 split-precision solve timed to 1e-6 Ha
+    against it."""
+    w = synthetic.WORKLOADS["sphere_r18_h0.18_cage60"]
+    log("cage: FP64 plain run")
+    r64 = eigensolve_run(w, "f64", w.block, max_steps, 1e-6)
+    ref = r64["eig"]
+    keep = r64["keep"]
+    for k, (t, e) in enumerate(zip(r64["times"], r64["eigs"])):
+        if np.max(np.abs(e[:keep] - ref[:keep])) < 1e-6:
+            r64["t_hit"], r64["k_hit"] = t, k + 1
+            break
+    log("cage: FP32 split-precision run")
+    r32 = eigensolve_run(w, "f32", w.block, max_steps, 1e-5, ref=ref, stop_at_hit=True)
+    return {
+        "workload": w.name, "states": w.nstates, "block": w.block, "measured_states": keep,
+        "reference": (f"FP64 run's end (max residual {r64['final_max_res']:.1e} after {r64['steps']} steps); "
+                      "parity unpinned: no independent solve at this size"),
+        "plain_fp64_filter": {"time_s": r64["t_hit"], "steps": r64["k_hit"], "ms_per_step": r64["ms_per_step"]},
+        "fp32_split_filter": {"time_s": r32["t_hit"], "steps": r32["k_hit"], "ms_per_step": r32["ms_per_step"],
+                              "final_max_eig_error_ha": float(np.max(np.abs(r32["eig"][:keep] - ref[:keep])))},
     }
 
 
@@ -395,6 +447,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-cage", action="store_true",
+                    help="skip the large-sphere lines (FP32 H psi throughput and the eigensolve comparison)")
     ap.add_argument("--profile-eig", type=int, default=0, metavar="K",
                     help="for kernel-trace runs: K eigensolver steps of the FP64 sphere and of "
                          "its FP32 split-precision form from the seeded start; prints step times")
@@ -434,10 +488,21 @@ def main():
         log(f"fp32: {r3}")
         extra[w3.name] = {k: r3[k] for k in ("ptstates_per_s", "gflops", "t_step",
                                                  "t_kernel", "achieved_gbs", "frac")}
+    if primary and not a.no_cage:
+        w5 = synthetic.WORKLOADS["sphere_r18_h0.18_cage60"]
+        r5 = run_gpu(w5, "f32", w5.block, a.steps, a.warmup)
+        log(f"cage fp32: {r5}")
+        extra[w5.name] = {k: r5[k] for k in ("ptstates_per_s", "gflops", "t_step", "t_kernel", "achieved_gbs",
+                                             "frac", "np", "N", "B", "nblk")}
+        extra[w5.name]["note"] = "240 states in 4 blocks of 64 (16 zero padding states, not counted)"
     eig = None
     if primary and not a.no_eig:
         eig = eigensolve_compare()
         log(f"eigensolve: {eig}")
+    cage = None
+    if primary and not a.no_eig and not a.no_cage:
+        cage = cage_compare()
+        log(f"cage eigensolve: {cage}")
     lrn = None
     if primary and not a.no_learned:
         log("learned preconditioner: periodic workload")
@@ -469,6 +534,7 @@ def main():
                      "bytes_per_launch": r["bytes_kernel"],
                      "avg_launch_s": r["t_kernel"]},
         "eigensolve": eig,
+        "eigensolve_cage": cage,
         "learned_preconditioner": lrn,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -340,6 +340,15 @@ void rs_cnn_destroy(rs_cnn *c);
 /* HOST float [RS_CNN_NPARAM]; setting also resets the Adam moments. */
 rs_status rs_cnn_set_params(rs_cnn *c, const float *params);
 rs_status rs_cnn_get_params(const rs_cnn *c, float *params);
+/* Checkpoint of the network's training state: the parameters, both Adam
+ * moments and the Adam step count, written to / read from the file at path
+ * (binary: an 8-byte tag "RSCNN001", int64 parameter count, int64 step
+ * count, then 3 * RS_CNN_NPARAM floats, little endian).  Loading restores
+ * the state exactly, so training resumes where it stopped.  RS_EINVAL when
+ * the file cannot be opened, is short, or holds another layout.
+ * Synchronous. */
+rs_status rs_cnn_save(const rs_cnn *c, const char *path);
+rs_status rs_cnn_load(rs_cnn *c, const char *path);
 
 /* f = network(u) for n boxes of dims {Z, Y, X}, no mask (all points
  * inside), zero outside the box or wrapped (periodic != 0).
@@ -394,14 +403,19 @@ rs_status rs_shifted_solve(const rs_grid *g, const void *r, const double *sigma,
                            int32_t nblk, int32_t B, int32_t dtype, double tol, int32_t maxit,
                            int32_t *iters, void *stream);
 
-/* Use the network as the solver's preconditioner (NULL: the filter).  Each
- * step then also applies the kinetic stencil to psi for the shifts
- * sigma_k = -<psi_k|T|psi_k>.  The filter stays the fallback and the judge,
- * per state: a state takes the filter's direction in a step where <r|K r>
- * is not positive and finite, and takes it for good (until the next
- * rs_eigensolve_set_precond) once its residual norm exceeds twice the
- * smallest residual norm it has had since the network was set.  The handle
- * must outlive its use. */
+/* Use the network as a second preconditioner of the solver (NULL: the
+ * filter alone).  Each step then also applies the kinetic stencil to psi for
+ * the shifts sigma_k = -<psi_k|T|psi_k>, and per active state the trial step
+ * minimises the Rayleigh quotient over span{psi, d_f, d_n}, d_f = K_f R0
+ * (filter) and d_n = K_n R0 (network): the lowest eigenvector of that 3x3
+ * generalised problem (first component one) gives the coefficients (a, b)
+ * of K = a K_f + b K_n, which is the state's preconditioner for the rest of
+ * the step (lambda = 1).  The filter thus stays in every trial subspace and
+ * judges the network state by state and step by step: a useless network
+ * gets b ~ 0.  When the 3x3 problem is singular (d_n zero, not finite or
+ * parallel to d_f) the state takes the filter step (b = 0).  Costs per step
+ * one more H application (H d_n) and m network applications.  Allocates two
+ * field arrays on first use.  The handle must outlive its use. */
 rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c);
 
 /* Counters of the last rs_eigensolve_step. */
@@ -409,8 +423,8 @@ typedef struct {
     int32_t steps;          /* steps taken by this solver                      */
     int32_t rr_sweeps;      /* Jacobi sweeps of its Rayleigh-Ritz problem      */
     int32_t frozen_blocks;  /* blocks frozen by the stopping rule              */
-    int32_t net_states;     /* states still preconditioned by the network (0
-                               when the filter is the preconditioner)          */
+    int32_t net_states;     /* states whose trial step gave the network a
+                               nonzero coefficient (0 with the filter alone)   */
 } rs_solver_stats;
 rs_status rs_eigensolve_stats(const rs_solver *s, rs_solver_stats *out);
 

@@ -83,3 +83,7 @@ void oracle_hpsi_f64(int64_t np, int nblk, int B,
         }
     }
 }
+
+/* Threads the parallel loops above use (the OpenMP default team size). */
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }

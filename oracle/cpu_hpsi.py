@@ -38,6 +38,27 @@ def _lib():
     return f
 
 
+def threads() -> int:
+    """OpenMP threads the C oracle's parallel loops use."""
+    if not os.path.exists(_LIB):
+        raise RuntimeError(f"{_LIB} not built; run oracle.cpu_hpsi.build()")
+    f = ctypes.CDLL(_LIB).oracle_threads
+    f.restype = ctypes.c_int
+    return int(f())
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or 'unknown'."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 class CpuHamiltonian:
     """Holds the flattened tables of an oracle Hamiltonian for the C kernel."""
 

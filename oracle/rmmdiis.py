@@ -33,6 +33,18 @@ points per edge the alternating vector (-1)^(i+j+k) is then an exact null
 vector of K: no update can change the states' components along it, and the
 random start's share of it stays in the residuals as a floor (~1e-2 on a
 periodic 48^3 box).  alpha = 0.6 keeps the symbol >= 0.2.
+
+With a learned preconditioner K_n (the project's addition, ``oracle.cnn``)
+the network does not replace the filter K_f: it adds a second direction.
+The trial step minimises the Rayleigh quotient over span{psi0, d_f, d_n},
+d_f = K_f R0, d_n = K_n R0 (lowest eigenpair of the 3x3 generalised problem
+in the basis {psi0, d_f/|d_f|, d_n/|d_n|}, first component scaled to one),
+which gives per state the coefficients (a, b) of K = a K_f + b K_n.  That K
+is the state's preconditioner for the rest of the step, with lambda = 1:
+psi1 = psi0 + K R0 and psi_{j+1} = psibar + K Rbar.  The filter is always in
+the trial subspace, so a useless network gets b ~ 0 and the step is the
+filter's; when the 3x3 problem is singular (d_n parallel to d_f, zero or not
+finite) the state takes the filter step of step 2 (b = 0).
 """
 from __future__ import annotations
 
@@ -107,9 +119,36 @@ def trial_lambda(a11, a12, a22, b11, b12, b22) -> float:
     return float(y / x * s)
 
 
-def rmmdiis_step(H, psi: np.ndarray, opts: Options):
-    """One eigensolver step.  psi [N, np] orthonormal on entry.
-    Returns dict(psi, eig, resnorm, active, lam)."""
+def trial_mix(A: np.ndarray, Bm: np.ndarray):
+    """Coefficients (a, b) of the filter and network directions minimising
+    the Rayleigh quotient of psi + a d_f + b d_n; A, Bm [3, 3] are
+    <v_i|H|v_j> and <v_i|v_j> for v = (psi, d_f, d_n).  None when the
+    problem is singular."""
+    n = np.sqrt(np.diag(Bm))
+    if not (n[1] > 0.0 and n[2] > 0.0) or not np.all(np.isfinite(A)) or not np.all(np.isfinite(Bm)):
+        return None
+    D = np.array([1.0, 1.0 / n[1], 1.0 / n[2]])
+    try:
+        mu, vec = scipy.linalg.eigh(A * np.outer(D, D), Bm * np.outer(D, D))
+    except np.linalg.LinAlgError:
+        return None
+    v = vec[:, 0]
+    if v[0] == 0.0 or not np.all(np.isfinite(v)):
+        return None
+    return float(v[1] / v[0] * D[1]), float(v[2] / v[0] * D[2])
+
+
+def kinetic_shifts(H, psi: np.ndarray) -> np.ndarray:
+    """sigma_k = -<psi_k|T psi_k> / <psi_k|psi_k> (the learned
+    preconditioner's shifts)."""
+    dv = H.dv
+    return -dots(psi, H.apply_kinetic(psi), dv) / dots(psi, psi, dv)
+
+
+def rmmdiis_step(H, psi: np.ndarray, opts: Options, net: Optional[np.ndarray] = None):
+    """One eigensolver step.  psi [N, np] orthonormal on entry; net: the
+    learned preconditioner's parameters (oracle.cnn), or None for the filter
+    alone.  Returns dict(psi, eig, resnorm, active, lam, mix)."""
     dv = H.dv
     g = H.g
     nbr = H.nbr
@@ -127,6 +166,7 @@ def rmmdiis_step(H, psi: np.ndarray, opts: Options):
             if np.all(res[b0:b0 + opts.block] < opts.tol):
                 active[b0:b0 + opts.block] = False
     lam = np.zeros(N)
+    mix = np.zeros((N, 2))
     if active.any():
         A = np.nonzero(active)[0]
         p0, h0, r0, e0 = psi[A], hpsi[A], R0[A], eps0[A]
@@ -140,7 +180,29 @@ def rmmdiis_step(H, psi: np.ndarray, opts: Options):
         b22 = dots(d, d, dv)
         lm = np.array([trial_lambda(a11[s], a12[s], a22[s], b11[s], b12[s], b22[s])
                        for s in range(len(A))])
+        cf, cn = lm.copy(), np.zeros(len(A))
+        if net is not None:
+            from . import cnn
+            sig = kinetic_shifts(H, psi)[A]
+            dn = cnn.precondition(net, g, r0, sig)
+            hdn = H.apply(dn)
+            for s in range(len(A)):
+                v = (p0[s], d[s], dn[s])
+                hv = (h0[s], hd[s], hdn[s])
+                Am = np.empty((3, 3))
+                Bq = np.empty((3, 3))
+                for i in range(3):
+                    for j in range(i, 3):
+                        Am[i, j] = Am[j, i] = 0.5 * dv * (v[i] @ hv[j] + v[j] @ hv[i])
+                        Bq[i, j] = Bq[j, i] = dv * (v[i] @ v[j])
+                ab = trial_mix(Am, Bq)
+                if ab is not None:
+                    cf[s], cn[s] = ab
+            lm = np.where(cn != 0.0, 1.0, lm)
+            d = np.where((cn != 0.0)[:, None], cf[:, None] * d + cn[:, None] * dn, d)
+            hd = np.where((cn != 0.0)[:, None], cf[:, None] * hd + cn[:, None] * hdn, hd)
         lam[A] = lm
+        mix[A, 0], mix[A, 1] = cf, cn
         hist_p = [p0, p0 + lm[:, None] * d]
         hist_h = [h0, h0 + lm[:, None] * hd]
         moving = lm != 0.0
@@ -168,24 +230,29 @@ def rmmdiis_step(H, psi: np.ndarray, opts: Options):
             hbar = sum(c[:, a, None] * hv[a] for a in range(n))
             rbar = sum(c[:, a, None] * rv[a] for a in range(n))
             d = filter_precond(g, rbar, nbr, opts.alpha)
+            if net is not None and np.any(cn != 0.0):
+                from . import cnn
+                use = cn != 0.0
+                dn = cnn.precondition(net, g, rbar, sig)
+                d = np.where(use[:, None], cf[:, None] * d + cn[:, None] * dn, d)
             hd = H.apply(d)
             hist_p.append(pbar + lm[:, None] * d)
             hist_h.append(hbar + lm[:, None] * hd)
         psi = psi.copy()
         psi[A] = hist_p[-1]
     psi, _, _ = orthonormalize(psi, dv)
-    return dict(psi=psi, eig=eig, resnorm=res, active=active, lam=lam)
+    return dict(psi=psi, eig=eig, resnorm=res, active=active, lam=lam, mix=mix)
 
 
 def eigensolve(H, psi: np.ndarray, opts: Options, max_steps: int,
-               eref: Optional[np.ndarray] = None, etol: float = 1e-6):
+               eref: Optional[np.ndarray] = None, etol: float = 1e-6, net: Optional[np.ndarray] = None):
     """Iterate rmmdiis_step from orthonormalised psi until every residual is
     below opts.tol (or, with eref, each of the lowest len(eref) eigenvalues
     is within etol of it)."""
     psi, _, _ = orthonormalize(psi, H.dv)
     hist = []
     for it in range(max_steps):
-        out = rmmdiis_step(H, psi, opts)
+        out = rmmdiis_step(H, psi, opts, net)
         psi = out["psi"]
         hist.append((out["eig"].copy(), out["resnorm"].copy()))
         if eref is not None:

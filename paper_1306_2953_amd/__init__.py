@@ -10,6 +10,7 @@ happens here.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -448,6 +449,14 @@ class Cnn:
         p = np.empty(self.NPARAM, dtype=np.float32)
         check(lib().rs_cnn_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
         return p
+
+    def save(self, path: str):
+        """Parameters, Adam moments and step count to a file (rs_cnn_save)."""
+        check(lib().rs_cnn_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Restores a checkpoint written by save (rs_cnn_load)."""
+        check(lib().rs_cnn_load(self._h, os.fsencode(path)))
 
     @staticmethod
     def _dims(t):

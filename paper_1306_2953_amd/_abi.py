@@ -76,6 +76,8 @@ SIGNATURES = {
     "rs_cnn_destroy": (None, [P]),
     "rs_cnn_set_params": (ctypes.c_int, [P, P]),
     "rs_cnn_get_params": (ctypes.c_int, [P, P]),
+    "rs_cnn_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+    "rs_cnn_load": (ctypes.c_int, [P, ctypes.c_char_p]),
     "rs_cnn_forward": (ctypes.c_int, [P, P, P, I32, PI32, I32, P]),
     "rs_cnn_loss_grad": (ctypes.c_int, [P, P, P, P, I32, PI32, F64, I32, PF64, P, P, P]),
     "rs_cnn_adam_step": (ctypes.c_int, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P]),

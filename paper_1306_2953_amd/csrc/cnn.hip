@@ -16,7 +16,9 @@
 // input offset (dx-1, dy-1, dz-1)), then a, b.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "colreduce.hpp"
@@ -621,6 +623,49 @@ extern "C" rs_status rs_cnn_set_params(rs_cnn *c, const float *params) {
 extern "C" rs_status rs_cnn_get_params(const rs_cnn *c, float *params) {
     if (!c || !params) return rs::fail(RS_EINVAL, "rs_cnn_get_params: null argument");
     RS_HIP(hipMemcpy(params, c->params.p, kNP * sizeof(float), hipMemcpyDeviceToHost));
+    return RS_OK;
+}
+
+// Checkpoint file: 8-byte tag, int64 parameter count, int64 Adam step count,
+// then the parameters and the two Adam moments (float each), little endian.
+namespace {
+constexpr char kCnnTag[8] = {'R', 'S', 'C', 'N', 'N', '0', '0', '1'};
+}
+
+extern "C" rs_status rs_cnn_save(const rs_cnn *c, const char *path) {
+    using rs::fail;
+    if (!c || !path) return fail(RS_EINVAL, "rs_cnn_save: null argument");
+    std::vector<float> buf(3 * (size_t)kNP);
+    RS_HIP(hipMemcpy(buf.data(), c->params.p, kNP * sizeof(float), hipMemcpyDeviceToHost));
+    RS_HIP(hipMemcpy(buf.data() + kNP, c->m.p, kNP * sizeof(float), hipMemcpyDeviceToHost));
+    RS_HIP(hipMemcpy(buf.data() + 2 * kNP, c->v.p, kNP * sizeof(float), hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(RS_EINVAL, std::string("rs_cnn_save: cannot open ") + path);
+    const int64_t hdr[2] = {(int64_t)kNP, c->adam_t};
+    bool ok = std::fwrite(kCnnTag, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int64_t), 2, f) == 2 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(RS_EINVAL, std::string("rs_cnn_save: write failed: ") + path);
+    return RS_OK;
+}
+
+extern "C" rs_status rs_cnn_load(rs_cnn *c, const char *path) {
+    using rs::fail;
+    if (!c || !path) return fail(RS_EINVAL, "rs_cnn_load: null argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(RS_EINVAL, std::string("rs_cnn_load: cannot open ") + path);
+    char tag[8];
+    int64_t hdr[2];
+    std::vector<float> buf(3 * (size_t)kNP);
+    const bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kCnnTag, 8) == 0 &&
+                    std::fread(hdr, sizeof(int64_t), 2, f) == 2 && hdr[0] == kNP && hdr[1] >= 0 &&
+                    std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(RS_EINVAL, std::string("rs_cnn_load: not a network checkpoint of this layout: ") + path);
+    RS_HIP(hipMemcpy(c->params.p, buf.data(), kNP * sizeof(float), hipMemcpyHostToDevice));
+    RS_HIP(hipMemcpy(c->m.p, buf.data() + kNP, kNP * sizeof(float), hipMemcpyHostToDevice));
+    RS_HIP(hipMemcpy(c->v.p, buf.data() + 2 * kNP, kNP * sizeof(float), hipMemcpyHostToDevice));
+    c->adam_t = hdr[1];
     return RS_OK;
 }
 

@@ -7,7 +7,11 @@
 //      residual norm.  A block whose states are all below tol is frozen.
 //   3. d = K R0 (filter), H d; the trial step lambda minimises the Rayleigh
 //      quotient of psi + lambda d (2x2 generalised problem per state);
-//      psi1 = psi + lambda d, H psi1 = H psi + lambda H d.
+//      psi1 = psi + lambda d, H psi1 = H psi + lambda H d.  With a learned
+//      preconditioner its direction d_n = K_n R0 joins the filter's: the
+//      Rayleigh quotient is minimised over span{psi, d_f, d_n} (3x3 problem
+//      per state), giving K = a K_f + b K_n for the state's step (lambda 1);
+//      a singular 3x3 problem leaves the state on the filter (b = 0).
 //   4. m - 1 DIIS iterations: residuals R_i = H psi_i - eps_i psi_i of the
 //      history; minimise |sum c R| / |sum c psi| over the history written in
 //      the basis {psi_L, psi_i - psi_L} (generalised eigenproblem per state,
@@ -91,6 +95,28 @@ template <typename T> struct OpLam {     // <x|Hd>, <d|Hx>, <d|Hd>, <x|d>, <d|d>
         a[2] += v * hv;
         a[3] += u * v;
         a[4] += v * v;
+    }
+};
+// The trial subspace {x, d, e} (filter and network directions): <x|Hd>,
+// <d|Hx>, <d|Hd>, <x|d>, <d|d>, the same five for e, then <d|He>, <e|Hd>,
+// <d|e>.
+template <typename T> struct OpLam3 {
+    const T *x, *hx, *d, *hd, *e, *he;
+    __device__ void operator()(int64_t i, int, double *a) const {
+        const double u = x[i], hu = hx[i], v = d[i], hv = hd[i], w = e[i], hw = he[i];
+        a[0] += u * hv;
+        a[1] += v * hu;
+        a[2] += v * hv;
+        a[3] += u * v;
+        a[4] += v * v;
+        a[5] += u * hw;
+        a[6] += w * hu;
+        a[7] += w * hw;
+        a[8] += u * w;
+        a[9] += w * w;
+        a[10] += v * hw;
+        a[11] += w * hv;
+        a[12] += v * w;
     }
 };
 // DIIS matrices over n = L + 1 iterates in the basis {x_L, x_i - x_L}:
@@ -285,6 +311,71 @@ __global__ void lambda_kernel(const double *__restrict__ d2, const double *__res
     lam[c] = l;
 }
 
+// Filter and network coefficients of the trial step (state frozen: lambda
+// 0).  d2: [<x|x>, <x|Hx>]; d13: the dots of OpLam3.  The Rayleigh quotient
+// is minimised over {x, d/|d|, e/|e|}; the lowest generalised eigenvector,
+// first component one, gives mix = (a, b) and lambda = 1.  When that 3x3
+// problem is singular the 2x2 filter step is kept: lambda from it, mix =
+// (lambda, 0).
+__global__ void mix_kernel(const double *__restrict__ d2, const double *__restrict__ d13,
+                           const int *__restrict__ active, int N, double *__restrict__ lam,
+                           double *__restrict__ mix) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    double l = 0.0, ma = 0.0, mb = 0.0;
+    const double bdd = d13[4 * N + c], bee = d13[9 * N + c];
+    if (active[c] && bdd > 0.0) {
+        const double s = 1.0 / sqrt(bdd);
+        const double a11 = d2[1 * N + c], b11 = d2[0 * N + c];
+        const double a12 = 0.5 * (d13[0 * N + c] + d13[1 * N + c]) * s;
+        const double a22 = d13[2 * N + c] * s * s;
+        const double b12 = d13[3 * N + c] * s;
+        {
+            const double A[4] = {a11, a12, a12, a22}, Bm[4] = {b11, b12, b12, 1.0};
+            double v[2];
+            if (lowest_geneig(2, A, Bm, v) && v[0] != 0.0) l = v[1] / v[0] * s;
+            ma = l;
+        }
+        if (bee > 0.0 && isfinite(bee)) {
+            const double t = 1.0 / sqrt(bee);
+            const double a13 = 0.5 * (d13[5 * N + c] + d13[6 * N + c]) * t;
+            const double a33 = d13[7 * N + c] * t * t;
+            const double b13 = d13[8 * N + c] * t;
+            const double a23 = 0.5 * (d13[10 * N + c] + d13[11 * N + c]) * s * t;
+            const double b23 = d13[12 * N + c] * s * t;
+            const double A[9] = {a11, a12, a13, a12, a22, a23, a13, a23, a33};
+            const double Bm[9] = {b11, b12, b13, b12, 1.0, b23, b13, b23, 1.0};
+            double v[3];
+            if (lowest_geneig(3, A, Bm, v) && v[0] != 0.0) {
+                ma = v[1] / v[0] * s;
+                mb = v[2] / v[0] * t;
+                l = 1.0;
+            }
+        }
+    }
+    lam[c] = l;
+    mix[c] = ma;
+    mix[N + c] = mb;
+}
+
+// d = a d + b e (and hd = a hd + b he when given) for the states whose
+// network coefficient b is nonzero.
+template <typename T>
+__global__ void __launch_bounds__(256)
+mixdir_kernel(T *__restrict__ d, const T *__restrict__ e, T *__restrict__ hd, const T *__restrict__ he,
+              const double *__restrict__ mix, int64_t np, int B, int N) {
+    // blockIdx.y: the block; B is a power of two
+    const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (il >= np * B) return;
+    const int64_t i = (int64_t)blockIdx.y * np * B + il;
+    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
+    const double b = mix[N + c];
+    if (b == 0.0) return;
+    const double a = mix[c];
+    d[i] = (T)(a * (double)d[i] + b * (double)e[i]);
+    if (hd) hd[i] = (T)(a * (double)hd[i] + b * (double)he[i]);
+}
+
 // eps of the newest iterate from its dots [<x|x>, <x|Hx>]
 __global__ void eps_kernel(const double *__restrict__ d2, int N, double *__restrict__ eps_out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,34 +416,8 @@ __global__ void sigma_kernel(const double *__restrict__ d2, int N, double *__res
     sigma[c] = nn > 0.0 ? -d2[1 * N + c] / nn : 0.0;
 }
 
-// Keep the learned direction d where the state still uses the network and
-// <r|d> (rd[N + c]) is positive and finite, else take the filter's alt.
-template <typename T>
-__global__ void __launch_bounds__(256)
-select_kernel(T *__restrict__ d, const T *__restrict__ alt, const double *__restrict__ rd,
-              const int *__restrict__ use_net, int64_t np, int B, int N) {
-    // blockIdx.y: the block; B is a power of two
-    const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (il >= np * B) return;
-    const int64_t i = (int64_t)blockIdx.y * np * B + il;
-    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
-    const double v = rd[N + c];
-    if (!use_net[c] || !(v > 0.0) || !isfinite(v)) d[i] = alt[i];
-}
-
-// The network is judged per state against its own record: a state whose
-// residual norm exceeds twice the smallest it has had takes the filter for
-// good.
-__global__ void net_reset_kernel(int N, int *__restrict__ use_net, double *__restrict__ best) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= N) return;
-    use_net[c] = 1;
-    best[c] = INFINITY;
-}
-
 __global__ void active_kernel(const double *__restrict__ rr, int N, int B, double tol, int block_stop,
-                              double *__restrict__ res, int *__restrict__ active, int judge,
-                              int *__restrict__ use_net, double *__restrict__ best) {
+                              double *__restrict__ res, int *__restrict__ active) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
     const double r = sqrt(rr[c]);
@@ -364,10 +429,6 @@ __global__ void active_kernel(const double *__restrict__ rr, int N, int B, doubl
         for (int k = b0; k < b0 + B; ++k) act |= !(sqrt(rr[k]) < tol);
     }
     active[c] = act;
-    if (judge) {
-        if (!(r <= 2.0 * best[c])) use_net[c] = 0;
-        best[c] = fmin(best[c], r);
-    }
 }
 
 }  // namespace
@@ -384,10 +445,10 @@ struct rs_solver {
     rs::DevBuf hx[kMaxHist], hh[kMaxHist];  // history of iterates and H applied
     rs::DevBuf R, d, hd, hpsi;
     rs::DevBuf partial, d2, d5, rr, res, eig, lam, eps, mats, coef, active;
-    rs::DevBuf sigma, R0, rd;    // shifts, recorded residuals, <r|K r>
-    rs::DevBuf use_net, best;    // per state: network still used, smallest residual so far
+    rs::DevBuf sigma, R0;        // shifts, recorded residuals
+    rs::DevBuf dn, hdn;          // network direction and H applied (with a network)
+    rs::DevBuf d13, mix;         // trial-subspace dots; filter / network coefficients
     rs_cnn *cnn = nullptr;
-    bool net_reset = false;      // use_net / best start over at the next step
     int rr_sweeps = kMaxSweeps;
     int steps = 0;
     rs_solver_stats stats{};
@@ -442,7 +503,7 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (!st) st = s->R.alloc(s->field_bytes);
     if (!st) st = s->d.alloc(s->field_bytes);
     if (!st) st = s->hd.alloc(s->field_bytes);
-    if (!st) st = s->partial.alloc(sizeof(double) * 12 * (size_t)nchunks * N);
+    if (!st) st = s->partial.alloc(sizeof(double) * 13 * (size_t)nchunks * N);
     if (!st) st = s->d2.alloc(sizeof(double) * 2 * N);
     if (!st) st = s->d5.alloc(sizeof(double) * 5 * N);
     if (!st) st = s->rr.alloc(sizeof(double) * N);
@@ -454,9 +515,8 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (!st) st = s->coef.alloc(sizeof(double) * kMaxHist * N);
     if (!st) st = s->active.alloc(sizeof(int) * N);
     if (!st) st = s->sigma.alloc(sizeof(double) * N);
-    if (!st) st = s->rd.alloc(sizeof(double) * 2 * N);
-    if (!st) st = s->use_net.alloc(sizeof(int) * N);
-    if (!st) st = s->best.alloc(sizeof(double) * N);
+    if (!st) st = s->d13.alloc(sizeof(double) * 13 * N);
+    if (!st) st = s->mix.alloc(sizeof(double) * 2 * N);
     if (!st && o.record) st = s->R0.alloc(s->field_bytes);
     if (st) {
         rs_ctx_destroy(s->ctx);
@@ -475,22 +535,18 @@ extern "C" void rs_eigensolve_destroy(rs_solver *s) {
 
 namespace {
 
-// d = K r: the filter, or the network with a per-state fallback to the
-// filter (computed into alt, which the caller overwrites afterwards).
+// d = K r for the DIIS iterations: the filter, or per state a K_f r + b K_n r
+// with the trial step's coefficients (the network output goes to S->dn).
 template <typename T>
-rs_status precond(rs_solver *S, const T *r, T *d, T *alt, hipStream_t st) {
+rs_status precond(rs_solver *S, const T *r, T *d, hipStream_t st) {
     using namespace rs;
     const rs_grid *g = S->g;
-    if (!S->cnn) return filter_apply(g, S->opts.alpha, r, d, S->nblk, S->B, S->dtype, st);
-    rs_status e;
-    if ((e = cnn_precondition(S->cnn, g, r, S->sigma.as<double>(), d, S->nblk, S->B, S->dtype, st))) return e;
-    if ((e = colreduce<2>(OpDots2<T>{r, d}, g->np, S->B, S->nblk, 1.0, S->partial.as<double>(), S->rd.as<double>(),
-                          st)))
-        return e;
-    if ((e = filter_apply(g, S->opts.alpha, r, alt, S->nblk, S->B, S->dtype, st))) return e;
+    rs_status e = filter_apply(g, S->opts.alpha, r, d, S->nblk, S->B, S->dtype, st);
+    if (e || !S->cnn) return e;
+    if ((e = cnn_precondition(S->cnn, g, r, S->sigma.as<double>(), S->dn.p, S->nblk, S->B, S->dtype, st))) return e;
     const dim3 gb((unsigned)((g->np * S->B + 255) / 256), S->nblk);
-    hipLaunchKernelGGL(select_kernel<T>, gb, dim3(256), 0, st, d, alt, S->rd.as<double>(), S->use_net.as<int>(),
-                       g->np, S->B, S->N);
+    hipLaunchKernelGGL(mixdir_kernel<T>, gb, dim3(256), 0, st, d, S->dn.as<T>(), (T *)nullptr, (const T *)nullptr,
+                       S->mix.as<double>(), g->np, S->B, S->N);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -512,11 +568,6 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     if ((e = subspace_diag_capped(S->ctx, psi, h0, S->eig.as<double>(), nblk, B, S->dtype, S->prec, S->rr_sweeps,
                                   S->nreal, st)))
         return e;
-    if (S->cnn && S->net_reset) {
-        hipLaunchKernelGGL(net_reset_kernel, dim3(gs), dim3(64), 0, st, N, S->use_net.as<int>(),
-                           S->best.as<double>());
-        S->net_reset = false;
-    }
     // shifts for the learned preconditioner: sigma = -<psi|T psi>
     if (S->cnn || S->opts.record) {
         if ((e = kinetic_apply(g, psi, S->d.p, nblk, B, S->dtype, st))) return e;
@@ -531,17 +582,32 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
                           S->rr.as<double>(), st)))
         return e;
     hipLaunchKernelGGL(active_kernel, dim3(gs), dim3(64), 0, st, S->rr.as<double>(), N, B, S->opts.tol,
-                       S->opts.block_stop, S->res.as<double>(), S->active.as<int>(), S->cnn ? 1 : 0,
-                       S->use_net.as<int>(), S->best.as<double>());
+                       S->opts.block_stop, S->res.as<double>(), S->active.as<int>());
     if (S->opts.record) RS_HIP(hipMemcpyAsync(S->R0.p, S->R.p, S->field_bytes, hipMemcpyDeviceToDevice, st));
     // 3. trial step
-    if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
+    if ((e = filter_apply(g, S->opts.alpha, S->R.p, S->d.p, nblk, B, S->dtype, st))) return e;
     if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
-    if ((e = colreduce<5>(OpLam<T>{psi, h0, S->d.as<T>(), S->hd.as<T>()}, np, B, nblk, dv, partial,
-                          S->d5.as<double>(), st)))
-        return e;
-    hipLaunchKernelGGL(lambda_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d5.as<double>(),
-                       S->active.as<int>(), N, S->lam.as<double>());
+    if (!S->cnn) {
+        if ((e = colreduce<5>(OpLam<T>{psi, h0, S->d.as<T>(), S->hd.as<T>()}, np, B, nblk, dv, partial,
+                              S->d5.as<double>(), st)))
+            return e;
+        hipLaunchKernelGGL(lambda_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d5.as<double>(),
+                           S->active.as<int>(), N, S->lam.as<double>());
+    } else {
+        // the network's direction and the 3x3 trial problem; the mixed
+        // direction replaces d (and H d) for the states that use it
+        if ((e = cnn_precondition(S->cnn, g, S->R.p, S->sigma.as<double>(), S->dn.p, nblk, B, S->dtype, st)))
+            return e;
+        if ((e = hpsi_apply(g, S->nl, S->vloc, S->dn.p, S->hdn.p, nblk, B, S->dtype, st))) return e;
+        if ((e = colreduce<13>(OpLam3<T>{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->dn.as<T>(), S->hdn.as<T>()}, np,
+                               B, nblk, dv, partial, S->d13.as<double>(), st)))
+            return e;
+        hipLaunchKernelGGL(mix_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d13.as<double>(),
+                           S->active.as<int>(), N, S->lam.as<double>(), S->mix.as<double>());
+        hipLaunchKernelGGL(mixdir_kernel<T>, gb, dim3(256), 0, st, S->d.as<T>(), S->dn.as<T>(), S->hd.as<T>(),
+                           S->hdn.as<T>(), S->mix.as<double>(), np, B, N);
+        RS_HIP(hipGetLastError());
+    }
     // history: iterate 0 is psi itself
     const T *xs[kMaxHist], *hs[kMaxHist];
     xs[0] = psi;
@@ -588,7 +654,7 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
             hipLaunchKernelGGL((combine_kernel<T, 3>), gb, dim3(256), 0, st, hist, S->eps.as<double>(),
                                S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N);
         RS_HIP(hipGetLastError());
-        if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), S->hd.as<T>(), st))) return e;
+        if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), st))) return e;
         if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
         if (n < m) {
             if ((e = colreduce<2>(OpAxpy2Dots<T>{xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb, S->lam.as<double>()},
@@ -620,20 +686,23 @@ extern "C" rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, do
     e = orthonormalize_impl(s->ctx, psi, s->nblk, s->B, s->dtype, s->prec, nullptr, &info, s->nreal, st);
     const int n = s->nreal;
     std::vector<double> ev(n), rn(n);
-    std::vector<int> act(s->N), net(s->N);
+    std::vector<int> act(s->N);
+    std::vector<double> mixb(s->cnn ? s->N : 0);
     int sweeps = 0;
     RS_HIP(hipMemcpyAsync(ev.data(), s->eig.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     RS_HIP(hipMemcpyAsync(rn.data(), s->res.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     RS_HIP(hipMemcpyAsync(act.data(), s->active.p, sizeof(int) * s->N, hipMemcpyDeviceToHost, st));
     RS_HIP(hipMemcpyAsync(&sweeps, ctx_sweeps(s->ctx), sizeof(int), hipMemcpyDeviceToHost, st));
-    if (s->cnn) RS_HIP(hipMemcpyAsync(net.data(), s->use_net.p, sizeof(int) * s->N, hipMemcpyDeviceToHost, st));
+    if (s->cnn)
+        RS_HIP(hipMemcpyAsync(mixb.data(), s->mix.as<double>() + s->N, sizeof(double) * s->N, hipMemcpyDeviceToHost,
+                              st));
     RS_HIP(hipStreamSynchronize(st));
     s->stats.rr_sweeps = sweeps;
     s->stats.frozen_blocks = 0;
     for (int b = 0; b < s->nblk; ++b) s->stats.frozen_blocks += act[(size_t)b * s->B] == 0;
     s->stats.net_states = 0;
     if (s->cnn)
-        for (int k = 0; k < n; ++k) s->stats.net_states += net[k] != 0;
+        for (int k = 0; k < n; ++k) s->stats.net_states += mixb[k] != 0.0;
     if (eig) std::memcpy(eig, ev.data(), sizeof(double) * n);
     if (resnorm) std::memcpy(resnorm, rn.data(), sizeof(double) * n);
     int c = 0;
@@ -655,8 +724,12 @@ extern "C" rs_status rs_eigensolve_stats(const rs_solver *s, rs_solver_stats *ou
 
 extern "C" rs_status rs_eigensolve_set_precond(rs_solver *s, rs_cnn *c) {
     if (!s) return rs::fail(RS_EINVAL, "rs_eigensolve_set_precond: null solver");
+    if (c && !s->dn.p) {
+        rs_status st = s->dn.alloc(s->field_bytes);
+        if (!st) st = s->hdn.alloc(s->field_bytes);
+        if (st) return st;
+    }
     s->cnn = c;
-    s->net_reset = c != nullptr;
     return RS_OK;
 }
 

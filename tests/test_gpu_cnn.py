@@ -182,3 +182,32 @@ def test_bad_arguments_raise():
     g = rsd.Grid("periodic", 0.25, n=16)                          # box 4096 > max_box
     with pytest.raises(rsd.RsError):
         net.precondition(g, _dev(np.zeros((1, g.np, 2), np.float32)), _dev(-np.ones(2)))
+
+
+def test_checkpoint_restores_training_state(tmp_path):
+    """save/load carry the parameters, both Adam moments and the step count:
+    after a restore, the next Adam step gives the same parameters as on the
+    network that was saved; a file of another layout is refused."""
+    p = _params(8, scale=0.2)
+    a = rsd.Cnn(4, 4096)
+    a.set_params(p)
+    u = _dev(np.random.default_rng(1).normal(size=(2, 8, 8, 8)), np.float32)
+    t = _dev(np.random.default_rng(2).normal(size=(2, 8, 8, 8)), np.float32)
+    sig = _dev(np.array([-1.0, -2.0]))
+    for _ in range(3):
+        a.loss_grad(u, t, sig, 0.25, 1)
+        a.adam_step(1e-3)
+    path = str(tmp_path / "net.rscnn")
+    a.save(path)
+    b = rsd.Cnn(4, 4096)
+    b.load(path)
+    assert np.array_equal(a.get_params(), b.get_params())
+    for net in (a, b):
+        net.loss_grad(u, t, sig, 0.25, 1)
+        net.adam_step(1e-3)
+    assert np.array_equal(a.get_params(), b.get_params())
+    bad = tmp_path / "bad.rscnn"
+    bad.write_bytes(b"RSCNN001" + b"\0" * 16)
+    with pytest.raises(rsd.RsError) as e:
+        b.load(str(bad))
+    assert e.value.code == rsd._abi.RS_EINVAL

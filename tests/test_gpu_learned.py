@@ -1,14 +1,20 @@
-"""What the trained network gains over the filter (A/B on the same seeds).
+"""The learned preconditioner inside the eigensolver.
 
-The network is trained on the GPU by the library's own kernels on pairs the
-method generates (residuals of plain filter steps and their shifted-kinetic
-CG solutions), then both preconditioners run the same number of RMM-DIIS
-steps from the same start on a small periodic system (32^3 points, h 0.25,
-four wells with projectors, 32 FP32 states).  The gain has no pin in the
-paper: the assertion is the measured improvement, with a wide margin.  The
-run is deterministic (fixed seeds, fixed-order reductions).  A shorter
-schedule (8 000 steps) gave a network whose solve stalled, so the test
-trains for 20 000 steps and asks for a validation loss below 0.05."""
+1. Parity: one step with a network (fixed random weights) against the
+   oracle's step with the same weights.  The network joins the filter in a
+   3x3 Rayleigh-quotient problem per state; the GPU network runs in FP32
+   (its output within 2e-5 of the oracle's, checked in the CNN tests) and
+   enters the states scaled by its coefficient b, so the updated states
+   are compared to 1e-6 (measured: 2e-8 to 4e-8) and everything computed
+   before the network (eigenvalues, residual norms) to the FP64 bounds.
+2. What the trained network gains over the filter (A/B on the same seeds):
+   the network is trained on the GPU by the library's own kernels on pairs
+   the method generates (residuals of plain filter steps and their
+   shifted-kinetic CG solutions); both solves then run from the same start
+   on a small periodic system (32^3 points, h 0.25, four wells with
+   projectors, 32 FP32 states).  The gain has no pin in the paper: the
+   assertion is the measured steps to a residual tolerance.  The run is
+   deterministic (fixed seeds, fixed-order reductions)."""
 import numpy as np
 import pytest
 
@@ -39,14 +45,53 @@ def _system():
     return w, g, nl, tv, tp
 
 
-def _solve(w, g, nl, tv, psi0, net, steps):
-    s = rsd.Eigensolver(g, nl, tv, w.nstates, w.block, tol=1e-4)
+def _steps_to(w, g, nl, tv, psi0, net, steps, tol):
+    s = rsd.Eigensolver(g, nl, tv, w.nstates, w.block, tol=1e-7)
     if net is not None:
         s.set_precond(net)
     x = psi0.clone()
-    for _ in range(steps):
+    for k in range(steps):
         eig, res, _ = s.step(x)
-    return eig, res
+        if np.median(res[:w.nstates - 4]) < tol:
+            return k + 1, res
+    return None, res
+
+
+@pytest.mark.parametrize("kind", ["periodic", "sphere"])
+def test_step_with_network_matches_oracle(kind):
+    from oracle import cnn as ocnn, hamiltonian, linalg, rmmdiis
+    if kind == "periodic":
+        w = synthetic.make_workload("periodic96_h0.25", n=16, nat=2, nstates=16, block=8)
+    else:
+        w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2, nstates=16, block=8)
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=16)
+    tv = torch.from_numpy(H.vloc).cuda()
+    rng = np.random.default_rng(3)
+    p = rng.normal(scale=0.2, size=ocnn.NP)
+    p[ocnn.NW], p[ocnn.NW + 1] = 0.3, -0.8
+    p = p.astype(np.float32).astype(np.float64)
+    psi, _, _ = linalg.orthonormalize(synthetic.draw_states(synthetic.rng_after_atoms(w), 16, og.np), og.dv)
+    opts = rmmdiis.Options(m=3, block=8, tol=1e-12)
+    for _ in range(2):                                 # away from the random start
+        psi = rmmdiis.rmmdiis_step(H, psi, opts)["psi"]
+    want = rmmdiis.rmmdiis_step(H, psi, opts, net=p)
+    box = int(np.prod(ocnn.box_of(og)[1]))
+    net = rsd.Cnn(16, box)
+    net.set_params(p)
+    s = rsd.Eigensolver(g, nl, tv, 16, 8, m=3, tol=1e-12)
+    s.set_precond(net)
+    t = torch.from_numpy(rsd.to_blocks(psi, 8)).cuda()
+    eig, res, _ = s.step(t)
+    got = rsd.from_blocks(t.cpu().numpy())
+    nmix = int(np.sum(want["mix"][:, 1] != 0.0))
+    perr = np.max(np.abs(got - want["psi"])) / np.max(np.abs(want["psi"]))
+    print(f"{kind}: states using the network {s.stats()['net_states']} (oracle {nmix}); psi err {perr:.2e}")
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert s.stats()["net_states"] == nmix and nmix > 0
+    assert perr < 1e-6
 
 
 def test_trained_network_beats_filter():
@@ -65,12 +110,11 @@ def test_trained_network_beats_filter():
     vloss = learned.evaluate(net, val, g.h, 3, 32)
     print(f"validation energy-norm loss {vloss:.3e}")
     assert vloss < 0.05
-    steps = 80
-    ef, rf = _solve(w, g, nl, tv, psi0, None, steps)
-    ec, rc = _solve(w, g, nl, tv, psi0, net, steps)
-    print(f"after {steps} steps: median residual filter {np.median(rf):.3e} network {np.median(rc):.3e}; "
-          f"lowest eigenvalue filter {ef[0]:.8f} network {ec[0]:.8f}")
-    assert np.all(np.isfinite(ec)) and np.all(np.isfinite(rc))
-    assert np.median(rc) < 0.25 * np.median(rf)
-    # the lowest eigenvalue is an upper bound: the better solve is lower
-    assert ec[0] < ef[0]
+    steps = 120
+    tol = 1e-4
+    kf, rf = _steps_to(w, g, nl, tv, psi0, None, steps, tol)
+    kn, rn = _steps_to(w, g, nl, tv, psi0, net, steps, tol)
+    print(f"steps to median residual {tol:g}: filter {kf}, filter + network {kn}; "
+          f"final median residual filter {np.median(rf):.3e} network {np.median(rn):.3e}")
+    assert kn is not None and kf is not None
+    assert kn <= kf

@@ -77,6 +77,75 @@ def test_trial_lambda_minimises_rayleigh_quotient():
         assert rq(lam) <= best.fun + 1e-10 * abs(best.fun)
 
 
+def test_trial_mix_minimises_rayleigh_quotient():
+    """The filter/network coefficients (a, b) of the learned trial step are
+    the minimiser of the Rayleigh quotient of psi + a d + b e: no point found
+    by Nelder-Mead from around them is lower, and a network direction that
+    is a multiple of the filter's is reported singular."""
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.25, nat=2, atom_radius=0.6, rc=1.0)
+    g, _, H = hamiltonian.build_system(w)
+    rng = np.random.default_rng(9)
+    dv = g.dv
+    for _ in range(3):
+        v = [rng.uniform(-1, 1, g.np) for _ in range(3)]
+        hv = [H.apply(x) for x in v]
+        A = np.array([[0.5 * dv * (v[i] @ hv[j] + v[j] @ hv[i]) for j in range(3)] for i in range(3)])
+        Bq = np.array([[dv * (v[i] @ v[j]) for j in range(3)] for i in range(3)])
+        a, b = rmmdiis.trial_mix(A, Bq)
+        def rq(t):
+            x = v[0] + t[0] * v[1] + t[1] * v[2]
+            return (x @ H.apply(x)) / (x @ x)
+        best = scipy.optimize.minimize(rq, [a, b], method="Nelder-Mead",
+                                       options=dict(xatol=1e-10, fatol=1e-14, maxiter=4000))
+        assert rq([a, b]) <= best.fun + 1e-10 * abs(best.fun)
+        A2 = A.copy(); B2 = Bq.copy()
+        A2[2], A2[:, 2] = 2 * A[1], 2 * A[:, 1]
+        A2[2, 2] = 4 * A[1, 1]
+        B2[2], B2[:, 2] = 2 * Bq[1], 2 * Bq[:, 1]
+        B2[2, 2] = 4 * Bq[1, 1]
+        assert rmmdiis.trial_mix(A2, B2) is None
+
+
+def test_step_with_zero_network_is_the_filter_step():
+    """A network that outputs zero (all weights zero) makes every 3x3 trial
+    problem singular, so the step with it is exactly the filter's step."""
+    from oracle import cnn
+    w = synthetic.make_workload("periodic96_h0.25", n=12, nat=1, nstates=8, block=4)
+    g, atoms, H = hamiltonian.build_system(w)
+    psi, _, _ = linalg.orthonormalize(synthetic.draw_states(synthetic.rng_after_atoms(w), 8, g.np), g.dv)
+    opts = rmmdiis.Options(m=3, block=4, tol=1e-12)
+    p = np.zeros(cnn.NP)
+    a = rmmdiis.rmmdiis_step(H, psi, opts)
+    b = rmmdiis.rmmdiis_step(H, psi, opts, net=p)
+    assert np.array_equal(a["psi"], b["psi"])
+    assert np.all(b["mix"][:, 1] == 0.0)
+
+
+def test_step_with_exact_inverse_beats_filter():
+    """A direction that the trial subspace can use well: with (T - sigma)^-1
+    r (the target the network is trained on, closed form on a periodic box)
+    standing in for the network, the step's Rayleigh quotients are never
+    above the filter step's and the network coefficient is nonzero."""
+    from oracle import cnn
+    w = synthetic.make_workload("periodic96_h0.25", n=12, nat=1, nstates=8, block=4)
+    g, atoms, H = hamiltonian.build_system(w)
+    psi, _, _ = linalg.orthonormalize(synthetic.draw_states(synthetic.rng_after_atoms(w), 8, g.np), g.dv)
+    opts = rmmdiis.Options(m=1, block=4, tol=1e-12)
+    orig = cnn.precondition
+    try:
+        cnn.precondition = lambda params, gg, r, sig: cnn.shifted_inverse_periodic(gg, r, sig)
+        withnet = rmmdiis.rmmdiis_step(H, psi, opts, net=np.zeros(cnn.NP))
+    finally:
+        cnn.precondition = orig
+    plain = rmmdiis.rmmdiis_step(H, psi, opts)
+    assert np.all(withnet["mix"][:, 1] != 0.0)
+    # m = 1: the returned states are the trial iterates, orthonormalised; the
+    # Rayleigh-Ritz values of the new subspace are lower with the network
+    def rr(x):
+        return linalg.rayleigh_ritz(x, H.apply(x), g.dv)[0]
+    assert np.sum(rr(withnet["psi"])) < np.sum(rr(plain["psi"]))
+
+
 def test_diis_coefficients_minimise_ratio():
     rng = np.random.default_rng(8)
     for n in (2, 3):
