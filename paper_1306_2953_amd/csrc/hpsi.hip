@@ -48,16 +48,14 @@ template <> __device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t o
 }
 // Cache policy of the field stores: non-temporal (the outputs are not read
 // again by this kernel, so they should not evict neighbour data from L2).
-#ifndef RS_STORE_AUX
-#define RS_STORE_AUX 2
-#endif
+constexpr int kStoreAux = 2;
 template <typename T> __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t off);
 template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, RS_STORE_AUX);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, kStoreAux);
 }
 template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, uint32_t off) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, RS_STORE_AUX);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, kStoreAux);
 }
 
 // Byte offset of the point in slot q of a brick (mask, start), scaled by
@@ -134,12 +132,12 @@ struct Slots {
             if constexpr (sizeof(T) == 4)
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r,
                                                       (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW),
-                                                      RS_STORE_AUX);
+                                                      kStoreAux);
             else {
                 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
                 __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r,
                                                       (int)(lane_off + (q % K) * ROW), (int)(base + (q / K) * K * ROW),
-                                                      RS_STORE_AUX);
+                                                      kStoreAux);
             }
         } else {
             bstore<T>(v, r, __builtin_elementwise_add_sat(lane_off, tbl[q]));
@@ -169,9 +167,7 @@ __device__ __forceinline__ void phase_fence(T (&acc)[N]) {
     __builtin_amdgcn_sched_barrier(0);
 }
 #define RS_PHASE() phase_fence(acc)
-#ifndef RS_PHASE_LINES
-#define RS_PHASE_LINES 4     // stencil lines per phase
-#endif
+constexpr int kPhaseLines = 4;     // stencil lines per phase
 
 // One wave computes NZ z-planes (from plane Z0) of one brick for 64 state
 // columns: lane l is state (c mod B) of block (c / B), c = 64*colgroup + l.
@@ -219,7 +215,7 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
             line_lap<T, 12, R>(v, lap, w0, w1, w2, w3);
 #pragma unroll
             for (int x = 0; x < 4; ++x) acc[(zz * 4 + y) * 4 + x] = lap[x];
-            if ((zz * 4 + y) % RS_PHASE_LINES == RS_PHASE_LINES - 1) RS_PHASE();
+            if ((zz * 4 + y) % kPhaseLines == kPhaseLines - 1) RS_PHASE();
         }
     // y lines
 #pragma unroll
@@ -237,7 +233,7 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
             line_lap<T, 12, R>(v, lap, w0, w1, w2, w3);
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[(zz * 4 + y) * 4 + x] += lap[y];
-            if ((zz * 4 + x) % RS_PHASE_LINES == RS_PHASE_LINES - 1) RS_PHASE();
+            if ((zz * 4 + x) % kPhaseLines == kPhaseLines - 1) RS_PHASE();
         }
     // z lines: NZ + 8 values around this wave's planes
 #pragma unroll
@@ -257,7 +253,7 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
             line_lap<T, NZ + 8, R>(v, lap, w0, w1, w2, w3);
 #pragma unroll
             for (int zz = 0; zz < NZ; ++zz) acc[(zz * 4 + y) * 4 + x] += lap[zz];
-            if ((y * 4 + x) % RS_PHASE_LINES == RS_PHASE_LINES - 1) RS_PHASE();
+            if ((y * 4 + x) % kPhaseLines == kPhaseLines - 1) RS_PHASE();
         }
     // local potential (or a constant when vloc is null)
 #pragma unroll
@@ -362,12 +358,11 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
 // z-marching kernel (the 25-point stencil of Sec. 5.1 plus the local
 // potential; the projector term is added by nl_add_kernel).  A work-group
 // owns one chunk: a column of 2 x 2 bricks (8 x 8 points in x-y) over nz
-// brick layers, for one group of SG state columns (SG * sizeof(T) = 128
-// bytes of each point row).  It walks the chunk plane by plane in z:
-//  - each thread owns PPT points (1, a 2 x 1 or a 2 x 2 block) of one state
-//    column and keeps the values of planes z-4 .. z+7 of those points in
-//    registers, so the z part of the stencil costs one load per output,
-//    issued three planes ahead;
+// brick layers, for one group of SG = 16 state columns (128 bytes of each
+// point row).  It walks the chunk plane by plane in z:
+//  - each thread owns one point of one state column and keeps the values of
+//    planes z-4 .. z+7 of that point in registers, so the z part of the
+//    stencil costs one load per output, issued three planes ahead;
 //  - the plane's 8 x 8 points and their x/y neighbours (4 deep on each side,
 //    128 points) are staged in LDS as a 16 x 16-point plane of 128-byte rows;
 //    the neighbour rows are fetched two planes ahead as 16-byte pieces.  Two
@@ -381,44 +376,30 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
 // same body.
 constexpr int kMW = 12;   // register window planes
 
-// Measured choices for the z-marching kernel: 128-byte state groups (64:
-// two work-groups per CU, but slower), FP64 one point per thread (1024
-// threads, 4 waves per SIMD; 2 and 4 points cost occupancy) in the plain
-// form, FP32 on the per-brick kernel (RS_MARCH_F32 1 runs it here, 2 points
-// per thread, first-difference form).
-#ifndef RS_MARCH_PLAIN64
-#define RS_MARCH_PLAIN64 1
-#endif
-#ifndef RS_MARCH_RB
-#define RS_MARCH_RB 128
-#endif
-#ifndef RS_MARCH_F32
-#define RS_MARCH_F32 0
-#endif
-#ifndef RS_MARCH_PPT32
-#define RS_MARCH_PPT32 2
-#endif
-#ifndef RS_MARCH_PPT64
-#define RS_MARCH_PPT64 1
-#endif
-template <typename T, int B, int SG, int PPT, bool FULL>
-__global__ void __launch_bounds__((64 / PPT) * SG)
+// Measured choices: 128-byte state groups (64-byte groups fit two
+// work-groups per CU but ran slower), one point per thread (1024 threads, 4
+// waves per SIMD; 2 or 4 points per thread need 182-256 VGPRs), the plain
+// form c0 v + sum c_m (v_-m + v_+m) (no cancellation concern in FP64).  FP32
+// fields run on the per-brick kernel above: a 2- or 4-point FP32 variant of
+// this kernel in the first-difference form measured 714 / 549 us per H psi
+// of 128 states on the 904k-point sphere against the per-brick 456 us.
+constexpr int kMarchSG = 16;              // FP64 state columns per work-group
+template <int B, bool FULL>
+__global__ void __launch_bounds__(64 * kMarchSG)
 hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__restrict__ tab, int nchunk,
-                  int nsg, int nwg_pad, const T *__restrict__ psi, T *__restrict__ hpsi, const T *__restrict__ vloc,
-                  T vconst, int64_t np, T pre, T w0, T w1, T w2, T w3) {
-    constexpr int NT = (64 / PPT) * SG;
-    constexpr int NI = PPT == 1 ? 1 : 2;         // the thread's points: NI x NJ in x-y
-    constexpr int NJ = PPT == 4 ? 2 : 1;
+                  int nsg, int nwg_pad, const double *__restrict__ psi, double *__restrict__ hpsi,
+                  const double *__restrict__ vloc, double vconst, int64_t np, double pre, double w0, double w1,
+                  double w2, double w3) {
+    typedef double T;
+    constexpr int SG = kMarchSG;
+    constexpr int NT = 64 * SG;
     constexpr int RB = SG * (int)sizeof(T);
     constexpr int ROWB = B * (int)sizeof(T);
     constexpr int NPC = RB / 16;                 // 16-byte pieces of a point row
     constexpr int KH = 128 * NPC / NT;           // neighbour pieces per thread and plane
     constexpr int PLANE = 256 * RB;
     constexpr int PH = 2;                        // planes of neighbour prefetch
-    constexpr bool PLAIN = sizeof(T) == 8 && RS_MARCH_PLAIN64;
-    static_assert(RB == 64 || RB == 128, "a state group is 64 or 128 bytes of a point row");
-    static_assert(PPT == 1 || PPT == 2 || PPT == 4, "1 x 1, 2 x 1 or 2 x 2 points per thread");
-    static_assert(KH >= 1 && 12 % PH == 0, "launch shape");
+    static_assert(RB == 128 && KH == 1 && 12 % PH == 0, "launch shape");
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * PLANE];
     __shared__ MarchBrick ltab[(kMarchCZ + 3) * 12];
@@ -434,9 +415,9 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
     for (int i = tid; i < (ch.nz + 3) * 12; i += NT) ltab[i] = tab[ch.tab + i];
     __syncthreads();
 
-    // thread: state column s of the group, block of NI x NJ points at (x0, y0)
+    // thread: state column s of the group, point (x0, y0) of the tile
     const int s = tid % SG, pg = tid / SG;
-    const int x0 = NI * (pg % (8 / NI)), y0 = NJ * (pg / (8 / NI));
+    const int x0 = pg % 8, y0 = pg / 8;
     const int opos = (x0 >> 2) + 2 * (y0 >> 2);
     const int oq = (y0 & 3) * 4 + (x0 & 3);
     const int blk = sg * SG / B, s0 = sg * SG % B;
@@ -487,12 +468,10 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
         if constexpr (FULL) return (uint32_t)r * rowb + extra;
         else return r < 0 ? kOOB : (uint32_t)r * rowb + extra;
     };
-    // own point k: (x0 + k % NI, y0 + k / NI)
-    auto load_own = [&](int p, T (&w)[PPT]) {
+    // the thread's point in plane p
+    auto load_own = [&](int p, T &w) {
         const MarchBrick mb = ltab[(p >> 2) * 12 + opos];
-        const int q0 = (p & 3) * 16 + oq;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) w[k] = bload<T>(rp, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), loff, ROWB));
+        w = bload<T>(rp, roff(prow(mb, (p & 3) * 16 + oq), loff, ROWB));
     };
     auto load_halo = [&](int p, u32x4 (&h)[KH]) {
 #pragma unroll
@@ -501,17 +480,14 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
             h[k] = __builtin_amdgcn_raw_buffer_load_b128(rp, (int)roff(prow(mb, (p & 3) * 16 + hq[k]), hc, ROWB), 0, 0);
         }
     };
-    auto load_v = [&](int p, T (&v)[PPT]) {
+    auto load_v = [&](int p, T &v) {
         const MarchBrick mb = ltab[(p >> 2) * 12 + opos];
-        const int q0 = (p & 3) * 16 + oq;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k)
-            v[k] = bload<T>(rv, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), 0u, (uint32_t)sizeof(T)));
+        v = bload<T>(rv, roff(prow(mb, (p & 3) * 16 + oq), 0u, (uint32_t)sizeof(T)));
     };
 
-    T win[kMW][PPT];
+    T win[kMW];
     u32x4 hreg[PH][KH];
-    T vreg[3][PPT];
+    T vreg[3];
     const int zend = 4 + 4 * ch.nz;            // output planes [4, zend) of the chunk's numbering
 
     // prologue: window planes 0 .. 10, neighbours of planes 4 .. 3 + PH, V
@@ -535,9 +511,7 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
         constexpr int vs = (4 + K) % 3;                   // V ring slot of plane z
         unsigned char *pl = lds + (K & 1) * PLANE;
         // stage plane z: own values from the window, neighbours from the ring
-#pragma unroll
-        for (int k = 0; k < PPT; ++k)
-            *(T *)(pl + ((y0 + k / NI + 4) * 16 + x0 + k % NI + 4) * RB + s * sizeof(T)) = win[c0][k];
+        *(T *)(pl + ((y0 + 4) * 16 + x0 + 4) * RB + s * sizeof(T)) = win[c0];
 #pragma unroll
         for (int k = 0; k < KH; ++k) *(u32x4 *)(pl + hlds[k]) = hreg[hs][k];
         // prefetch: window plane z + 7, neighbours of plane z + PH, V of z + 2
@@ -547,67 +521,20 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
         __syncthreads();
         const unsigned char *L = pl + (y0 * 16 + x0) * RB + s * sizeof(T);   // point (x0 - 4, y0 - 4)
         auto at = [&](int dx, int dy) -> T { return *(const T *)(L + ((dy + 4) * 16 + dx + 4) * RB); };
-        T acc[PPT];
-        if constexpr (PLAIN) {
-            // FP64: the plain form c0 v + sum_m c_m (v_-m + v_+m) per axis, with
-            // c_m = W_(m-1) - W_m (W_4 = 0) and c0 = -2 W_0; no cancellation
-            // concern at this precision and about half the operations
-            const T c1 = w0 - w1, c2 = w1 - w2, c3 = w2 - w3, c4 = w3, c0x3 = T(-6) * w0;
-            const T cc[5] = {T(0), c1, c2, c3, c4};
+        // c0 v + sum_m c_m (v_-m + v_+m) per axis, c_m = W_(m-1) - W_m
+        // (W_4 = 0) and c0 = -2 W_0
+        const T c1 = w0 - w1, c2 = w1 - w2, c3 = w2 - w3, c4 = w3, c0x3 = T(-6) * w0;
+        const T cc[5] = {T(0), c1, c2, c3, c4};
+        T sum = c0x3 * win[c0];
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int i = k % NI, j = k / NI;
-                auto X = [&](int ii) -> T { return (ii >= 0 && ii < NI) ? win[c0][ii + NI * j] : at(ii, j); };
-                auto Y = [&](int jj) -> T { return (jj >= 0 && jj < NJ) ? win[c0][i + NI * jj] : at(i, jj); };
-                T sum = c0x3 * win[c0][k];
-#pragma unroll
-                for (int m = 1; m <= 4; ++m) {
-                    sum += cc[m] * (X(i - m) + X(i + m));
-                    sum += cc[m] * (Y(j - m) + Y(j + m));
-                    sum += cc[m] * (win[(c0 + kMW - m) % kMW][k] + win[(c0 + m) % kMW][k]);
-                }
-                acc[k] = pre * sum + (vreg[vs][k] + vconst) * win[c0][k];
-            }
-        } else {
-        // x lines: the thread's NJ rows of NI points
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            T v[8 + NI], lap[NI];
-#pragma unroll
-            for (int m = 0; m < 8 + NI; ++m)
-                v[m] = (m >= 4 && m < 4 + NI) ? win[c0][(m - 4) + NI * j] : at(m - 4, j);
-            line_lap<T, 8 + NI, 4>(v, lap, w0, w1, w2, w3);
-#pragma unroll
-            for (int i = 0; i < NI; ++i) acc[i + NI * j] = lap[i];
+        for (int m = 1; m <= 4; ++m) {
+            sum += cc[m] * (at(-m, 0) + at(m, 0));
+            sum += cc[m] * (at(0, -m) + at(0, m));
+            sum += cc[m] * (win[(c0 + kMW - m) % kMW] + win[(c0 + m) % kMW]);
         }
-        // y lines: NI columns of NJ points
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            T v[8 + NJ], lap[NJ];
-#pragma unroll
-            for (int m = 0; m < 8 + NJ; ++m)
-                v[m] = (m >= 4 && m < 4 + NJ) ? win[c0][i + NI * (m - 4)] : at(i, m - 4);
-            line_lap<T, 8 + NJ, 4>(v, lap, w0, w1, w2, w3);
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) acc[i + NI * j] += lap[j];
-        }
-        // z lines from the window, then the potential
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            T v[9], lap[1];
-#pragma unroll
-            for (int m = 0; m < 9; ++m) v[m] = win[(c0 + kMW - 4 + m) % kMW][k];
-            line_lap<T, 9, 4>(v, lap, w0, w1, w2, w3);
-            acc[k] = pre * (acc[k] + lap[0]) + (vreg[vs][k] + vconst) * win[c0][k];
-        }
-        }
+        const T acc = pre * sum + (vreg[vs] + vconst) * win[c0];
         const MarchBrick mb = ltab[(z >> 2) * 12 + opos];
-        const int q0 = (z & 3) * 16 + oq;
-        if (FULL || mb.id >= 0) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                bstore<T>(acc[k], rh, roff(prow(mb, q0 + (k / NI) * 4 + k % NI), loff, ROWB));
-        }
+        if (FULL || mb.id >= 0) bstore<T>(acc, rh, roff(prow(mb, (z & 3) * 16 + oq), loff, ROWB));
     };
     int zb = 4;
     for (; zb + kMW <= zend; zb += kMW) {
@@ -768,15 +695,9 @@ nl_apply_kernel(const int32_t *__restrict__ pt_ptr, const int32_t *__restrict__ 
     *y = *y + acc;
 }
 
-#ifndef RS_MARCH
-#define RS_MARCH 1
-#endif
-#ifndef RS_NZF32
-#define RS_NZF32 2
-#endif
-#ifndef RS_NZF64
-#define RS_NZF64 1
-#endif
+// z planes per wave of the per-brick kernel on interior bricks (FP64, FP32)
+// and on the others
+constexpr int kNZF64 = 1, kNZF32 = 2, kNZS64 = 1, kNZS32 = 2;
 
 bool pow2_block(int B) { return B >= 1 && B <= 64 && (B & (B - 1)) == 0; }
 
@@ -832,11 +753,10 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
     const int nat = with_nl ? nl->nat : 0;
     const T w0 = (T)w[0], w1 = (T)w[1], w2 = (T)w[2], w3 = (T)w[3];
     // z-marching kernel (FP64): the full stencil when the block splits into
-    // state groups of RS_MARCH_RB = 128 bytes (B = 16, 32, 64)
-    if constexpr (R == 4 && RS_MARCH && (sizeof(T) == 8 || RS_MARCH_F32)) {
-        constexpr int SG = RS_MARCH_RB / (int)sizeof(T);
-        constexpr int PPT = sizeof(T) == 8 ? RS_MARCH_PPT64 : RS_MARCH_PPT32;
-        constexpr int NT = (64 / PPT) * SG;
+    // state groups of 16 columns (B = 16, 32, 64)
+    if constexpr (R == 4 && sizeof(T) == 8) {
+        constexpr int SG = kMarchSG;
+        constexpr int NT = 64 * SG;
         const int64_t nsg = (int64_t)nblk * B / SG;
         if (g->nmarch > 0 && B % SG == 0 && g->nmarch * nsg < (1ll << 30)) {
             for (int pass = 0; pass < 2; ++pass) {
@@ -850,11 +770,11 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
     case BB:                                                                                         \
         if constexpr (BB % SG == 0) {                                                                \
             if (full)                                                                                \
-                hipLaunchKernelGGL((hpsi_march_kernel<T, BB, SG, PPT, true>), grid, dim3(NT), 0, st, mc, \
+                hipLaunchKernelGGL((hpsi_march_kernel<BB, true>), grid, dim3(NT), 0, st, mc,         \
                                    g->march_tab.as<MarchBrick>(), (int)n, (int)nsg, nwg_pad, psi, hpsi, vloc, vconst, \
                                    g->np, pre, w0, w1, w2, w3);                                      \
             else                                                                                     \
-                hipLaunchKernelGGL((hpsi_march_kernel<T, BB, SG, PPT, false>), grid, dim3(NT), 0, st, mc, \
+                hipLaunchKernelGGL((hpsi_march_kernel<BB, false>), grid, dim3(NT), 0, st, mc,        \
                                    g->march_tab.as<MarchBrick>(), (int)n, (int)nsg, nwg_pad, psi, hpsi, vloc, vconst, \
                                    g->np, pre, w0, w1, w2, w3);                                      \
         }                                                                                            \
@@ -877,8 +797,8 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
         }
     }
     // interior bricks: NZF planes per wave; surface bricks: NZS
-    constexpr int NZF = sizeof(T) == 8 ? RS_NZF64 : RS_NZF32;
-    constexpr int NZS = sizeof(T) == 8 ? 1 : 2;
+    constexpr int NZF = sizeof(T) == 8 ? kNZF64 : kNZF32;
+    constexpr int NZS = sizeof(T) == 8 ? kNZS64 : kNZS32;
     for (int pass = 0; pass < 2; ++pass) {
         const bool fast = pass == 0;
         const int64_t nexec = fast ? g->nfast : g->nbricks - g->nfast;
