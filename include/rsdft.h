@@ -82,6 +82,13 @@ int rs_version(void);
  *       RS_GRID_SPHERE:   points (i, j, k) h with i^2 + j^2 + k^2 <= Q, where
  *                         Q = q^2 if R/h equals an integer q to 1e-9 relative
  *                         and floor((R/h)^2) otherwise; zero outside.
+ *       RS_GRID_UNION:    the molecular grid of Sec. 2 (Fig. "struct"): the
+ *                         points (i, j, k) h inside at least one sphere of
+ *                         radius R around the natoms centres (X, Y, Z),
+ *                         ((i h - X)^2 + (j h - Y)^2) + (k h - Z)^2 <= R^2 in
+ *                         FP64 rounded as written; zero outside.  The
+ *                         lattice spans floor((min X - R)/h) ..
+ *                         ceil((max X + R)/h) per axis (plus 4 each side).
  * brick: sub-grid edge lengths (>= 1).  The kernels of this library require
  *        the default 4 x 4 x 4; other shapes only change the index map.
  * Ordering: bricks x fastest, then y, then z over the brick lattice (which
@@ -93,6 +100,7 @@ int rs_version(void);
 #define RS_GRID_BOX      0
 #define RS_GRID_PERIODIC 1
 #define RS_GRID_SPHERE   2
+#define RS_GRID_UNION    3
 
 typedef struct rs_grid rs_grid;
 
@@ -105,6 +113,8 @@ typedef struct {
     int32_t flags;     /* RS_GRID_HOST_ONLY: build the index map on  */
                        /* the host only (no device tables; field     */
                        /* calls on such a grid return RS_EINVAL)     */
+    int32_t natoms;    /* union: number of sphere centres (>= 1)   */
+    const double *centres;  /* union: HOST [natoms][3] bohr, copied */
 } rs_grid_desc;
 
 #define RS_GRID_HOST_ONLY 1

@@ -5,6 +5,10 @@ the density is negligible) and Sec. 5.1 (the 3-D to 1-D map enumerates the
 grid by small parallelepipedic sub-grids, Fig. "locality" (b)).
 
 Readings taken where the paper is silent:
+  * a molecular grid is the union of spheres of radius R around the atoms
+    (Sec. 2, Fig. "struct"): point (i,j,k) at (i h, j h, k h) is inner iff
+    ((x - X)^2 + (y - Y)^2) + (z - Z)^2 <= R^2 for some atom (X, Y, Z), in
+    FP64 rounded as written;
   * sphere membership is decided in integer arithmetic (point (i,j,k) at
     i*h from the centre is inner iff i^2+j^2+k^2 <= Q, Q = q^2 when R/h is an
     integer q to 1e-9 relative, else floor((R/h)^2));
@@ -35,7 +39,7 @@ def sphere_bound(radius: float, h: float) -> Tuple[int, int]:
 
 @dataclasses.dataclass
 class Grid:
-    kind: str                 # "box", "periodic", "sphere"
+    kind: str                 # "box", "periodic", "sphere", "union"
     h: float
     n: int                    # box edge (box/periodic), 0 for sphere
     M: int                    # stencil half-width (neighbours per side)
@@ -87,14 +91,38 @@ def _brick_key(u: np.ndarray, brick, nb) -> np.ndarray:
     return bid * (bx * by * bz) + sid
 
 
+def union_inside(centres: np.ndarray, radius: float, h: float, lo: np.ndarray, L: np.ndarray) -> np.ndarray:
+    """Membership [z, y, x] of the lattice points lo + (i, j, k) in the union
+    of the spheres of radius `radius` around `centres` [nat, 3]: written out
+    atom by atom over the whole lattice (brute force)."""
+    ax = [(np.arange(L[d]) + lo[d]).astype(np.float64) * h for d in range(3)]
+    inside = np.zeros((L[2], L[1], L[0]), dtype=bool)
+    r2 = radius * radius
+    for c in np.asarray(centres, dtype=np.float64):
+        dx = ax[0] - c[0]
+        dy = ax[1] - c[1]
+        dz = ax[2] - c[2]
+        d2 = (dx[None, None, :] * dx[None, None, :] + dy[None, :, None] * dy[None, :, None]) \
+            + dz[:, None, None] * dz[:, None, None]
+        inside |= d2 <= r2
+    return inside
+
+
 def build_grid(kind: str, h: float, n: int = 0, radius: float = 0.0,
-               brick=(4, 4, 4), M: int = 4) -> Grid:
-    """Enumerate inner and boundary points in sub-grid order (Sec. 5.1)."""
+               brick=(4, 4, 4), M: int = 4, centres: Optional[np.ndarray] = None) -> Grid:
+    """Enumerate inner and boundary points in sub-grid order (Sec. 5.1).
+    kind "union": the union of spheres of `radius` around `centres`."""
     brick = tuple(int(b) for b in brick)
     if kind == "sphere":
         q, Q = sphere_bound(radius, h)
         lo_in = np.array([-q] * 3)
         ext = 2 * q + 1
+        pad = M
+        centre = 0.0
+    elif kind == "union":
+        c = np.asarray(centres, dtype=np.float64)
+        lo_in = np.floor((c.min(axis=0) - radius) / h).astype(np.int64)
+        ext = np.ceil((c.max(axis=0) + radius) / h).astype(np.int64) - lo_in + 1
         pad = M
         centre = 0.0
     elif kind == "box":
@@ -111,7 +139,7 @@ def build_grid(kind: str, h: float, n: int = 0, radius: float = 0.0,
             raise ValueError("periodic edge must be a multiple of the brick")
     else:
         raise ValueError(kind)
-    L = np.array([ext + 2 * pad] * 3)
+    L = np.broadcast_to(np.asarray(ext) + 2 * pad, (3,)).astype(np.int64)
     lo = lo_in - pad
     nb = -(-L // np.array(brick))
 
@@ -121,6 +149,8 @@ def build_grid(kind: str, h: float, n: int = 0, radius: float = 0.0,
         r2 = (ax[2][:, None, None] ** 2 + ax[1][None, :, None] ** 2
               + ax[0][None, None, :] ** 2)
         inside = r2 <= Q
+    elif kind == "union":
+        inside = union_inside(c, radius, h, lo, L)
     else:
         inside = np.zeros((L[2], L[1], L[0]), dtype=bool)
         inside[pad:pad + ext, pad:pad + ext, pad:pad + ext] = True
@@ -164,6 +194,9 @@ def grid_for(workload, brick=(4, 4, 4)) -> Grid:
     w = workload
     if w.grid_kind == "sphere":
         return build_grid("sphere", w.h, radius=w.radius, brick=brick)
+    if w.grid_kind == "union":
+        import synthetic
+        return build_grid("union", w.h, radius=w.radius, brick=brick, centres=synthetic.draw_atoms(w).pos)
     return build_grid(w.grid_kind, w.h, n=w.n, brick=brick)
 
 

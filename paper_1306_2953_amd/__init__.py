@@ -17,9 +17,9 @@ import numpy as np
 
 from . import _abi
 from ._abi import (RS_F32, RS_F64, RS_GRID_BOX, RS_GRID_HOST_ONLY, RS_GRID_PERIODIC,
-                   RS_GRID_SPHERE, RS_PREC_BF16X3, RS_PREC_NATIVE, RsError, check, lib)
+                   RS_GRID_SPHERE, RS_GRID_UNION, RS_PREC_BF16X3, RS_PREC_NATIVE, RsError, check, lib)
 
-_KINDS = {"box": RS_GRID_BOX, "periodic": RS_GRID_PERIODIC, "sphere": RS_GRID_SPHERE}
+_KINDS = {"box": RS_GRID_BOX, "periodic": RS_GRID_PERIODIC, "sphere": RS_GRID_SPHERE, "union": RS_GRID_UNION}
 
 
 def _ptr(a: np.ndarray):
@@ -27,10 +27,11 @@ def _ptr(a: np.ndarray):
 
 
 class Grid:
-    """Index map of a uniform grid restricted to a box or sphere (rs_grid)."""
+    """Index map of a uniform grid restricted to a box, a sphere or a union
+    of spheres around atom centres (rs_grid)."""
 
     def __init__(self, kind: str, h: float, n: int = 0, radius: float = 0.0,
-                 brick: Sequence[int] = (4, 4, 4), host_only: bool = False):
+                 brick: Sequence[int] = (4, 4, 4), host_only: bool = False, centres=None):
         d = _abi.GridDesc()
         d.kind = _KINDS[kind]
         d.h = float(h)
@@ -39,6 +40,13 @@ class Grid:
         for a in range(3):
             d.brick[a] = int(brick[a])
         d.flags = RS_GRID_HOST_ONLY if host_only else 0
+        c = None
+        if centres is not None:
+            c = np.ascontiguousarray(centres, dtype=np.float64)
+            if c.ndim != 2 or c.shape[1] != 3:
+                raise ValueError("centres must be [natoms, 3]")
+            d.natoms = c.shape[0]
+            d.centres = c.ctypes.data_as(ctypes.c_void_p)
         self.kind, self.h, self.n, self.radius = kind, float(h), int(n), float(radius)
         self.host_only = host_only
         self._h = ctypes.c_void_p()
@@ -53,10 +61,14 @@ class Grid:
         self.lo = tuple(lo)
 
     @classmethod
-    def for_workload(cls, w, host_only: bool = False) -> "Grid":
+    def for_workload(cls, w, host_only: bool = False, brick: Sequence[int] = (4, 4, 4)) -> "Grid":
         if w.grid_kind == "sphere":
-            return cls("sphere", w.h, radius=w.radius, host_only=host_only)
-        return cls(w.grid_kind, w.h, n=w.n, host_only=host_only)
+            return cls("sphere", w.h, radius=w.radius, host_only=host_only, brick=brick)
+        if w.grid_kind == "union":
+            import synthetic
+            return cls("union", w.h, radius=w.radius, host_only=host_only, brick=brick,
+                       centres=synthetic.draw_atoms(w).pos)
+        return cls(w.grid_kind, w.h, n=w.n, host_only=host_only, brick=brick)
 
     @property
     def handle(self):

@@ -15,7 +15,7 @@ RS_OK, RS_EINVAL, RS_ENOTPOSDEF, RS_ENONFINITE, RS_EHIP, RS_ENOMEM, RS_ENOTSUP, 
 RS_CNN_NPARAM = 2162
 RS_F64, RS_F32 = 0, 1
 RS_PREC_NATIVE, RS_PREC_BF16X3 = 0, 1
-RS_GRID_BOX, RS_GRID_PERIODIC, RS_GRID_SPHERE = 0, 1, 2
+RS_GRID_BOX, RS_GRID_PERIODIC, RS_GRID_SPHERE, RS_GRID_UNION = 0, 1, 2, 3
 RS_GRID_HOST_ONLY = 1
 
 P = ctypes.c_void_p
@@ -38,7 +38,7 @@ class SolverStats(ctypes.Structure):
 
 class GridDesc(ctypes.Structure):
     _fields_ = [("kind", I32), ("h", F64), ("n", I32), ("radius", F64),
-                ("brick", I32 * 3), ("flags", I32)]
+                ("brick", I32 * 3), ("flags", I32), ("natoms", I32), ("centres", P)]
 
 
 # name -> (restype, argtypes); the list of exported entry points

@@ -43,16 +43,37 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
     g->host_only = (d->flags & RS_GRID_HOST_ONLY) != 0;
     for (int a = 0; a < 3; ++a) g->brick[a] = br[a];
 
-    int64_t lo_in = 0, ext = 0, pad = 0, Q = 0;
+    int64_t lo_in[3] = {0, 0, 0}, ext[3] = {0, 0, 0}, pad = 0, Q = 0;
     if (d->kind == RS_GRID_SPHERE) {
         if (!(d->radius > 0)) { delete g; return fail(RS_EINVAL, "sphere radius must be > 0"); }
         SphereRule r = sphere_rule(d->radius, d->h);
         if (r.q > 20000) { delete g; return fail(RS_EINVAL, "sphere too large"); }
-        lo_in = -r.q; ext = 2 * r.q + 1; pad = kReach; Q = r.Q;
+        for (int a = 0; a < 3; ++a) { lo_in[a] = -r.q; ext[a] = 2 * r.q + 1; }
+        pad = kReach; Q = r.Q;
         g->centre = 0.0;
+    } else if (d->kind == RS_GRID_UNION) {
+        if (!(d->radius > 0) || !std::isfinite(d->radius)) { delete g; return fail(RS_EINVAL, "sphere radius must be > 0"); }
+        if (d->natoms < 1 || !d->centres) { delete g; return fail(RS_EINVAL, "a union of spheres needs natoms >= 1 centres"); }
+        for (int a = 0; a < 3; ++a) {
+            double cmin = d->centres[a], cmax = d->centres[a];
+            for (int i = 1; i < d->natoms; ++i) {
+                const double c = d->centres[3 * i + a];
+                if (!std::isfinite(c)) { delete g; return fail(RS_EINVAL, "atom centres must be finite"); }
+                cmin = std::min(cmin, c);
+                cmax = std::max(cmax, c);
+            }
+            if (!std::isfinite(cmin) || !std::isfinite(cmax)) { delete g; return fail(RS_EINVAL, "atom centres must be finite"); }
+            const double flo = std::floor((cmin - d->radius) / d->h), fhi = std::ceil((cmax + d->radius) / d->h);
+            if (!(fhi - flo < 40000.0)) { delete g; return fail(RS_EINVAL, "union of spheres too large"); }
+            lo_in[a] = (int64_t)flo;
+            ext[a] = (int64_t)fhi - lo_in[a] + 1;
+        }
+        pad = kReach;
+        g->centre = 0.0;
+        g->centres.assign(d->centres, d->centres + 3 * (size_t)d->natoms);
     } else if (d->kind == RS_GRID_BOX || d->kind == RS_GRID_PERIODIC) {
         if (d->n < 1 || d->n > 20000) { delete g; return fail(RS_EINVAL, "box edge out of range"); }
-        lo_in = 0; ext = d->n;
+        for (int a = 0; a < 3; ++a) { lo_in[a] = 0; ext[a] = d->n; }
         pad = d->kind == RS_GRID_BOX ? kReach : 0;
         g->centre = d->kind == RS_GRID_BOX ? 0.5 * (double)(d->n - 1) : 0.0;
         if (d->kind == RS_GRID_PERIODIC)
@@ -63,22 +84,46 @@ extern "C" rs_status rs_grid_create(const rs_grid_desc *d, rs_grid **out) {
         return fail(RS_EINVAL, "unknown grid kind");
     }
     for (int a = 0; a < 3; ++a) {
-        g->lo[a] = lo_in - pad;
-        g->L[a] = ext + 2 * pad;
+        g->lo[a] = lo_in[a] - pad;
+        g->L[a] = ext[a] + 2 * pad;
         g->nb[a] = (g->L[a] + br[a] - 1) / br[a];
     }
     const int64_t L0 = g->L[0], L1 = g->L[1], L2 = g->L[2];
     const int64_t ntot = L0 * L1 * L2;
     std::vector<uint8_t> inside(ntot, 0);
-    for (int64_t k = 0; k < L2; ++k)
-        for (int64_t j = 0; j < L1; ++j)
-            for (int64_t i = 0; i < L0; ++i) {
-                const int64_t x = i + g->lo[0], y = j + g->lo[1], z = k + g->lo[2];
-                bool in;
-                if (d->kind == RS_GRID_SPHERE) in = x * x + y * y + z * z <= Q;
-                else in = x >= 0 && x < ext && y >= 0 && y < ext && z >= 0 && z < ext;
-                inside[(k * L1 + j) * L0 + i] = in;
+    if (d->kind == RS_GRID_UNION) {
+        // each atom marks the lattice points of its sphere: ((x - X)^2 +
+        // (y - Y)^2) + (z - Z)^2 <= R^2 with x = i h, rounded as written
+        const double h = d->h, r2 = d->radius * d->radius;
+        for (int at = 0; at < d->natoms; ++at) {
+            const double *c = d->centres + 3 * at;
+            int64_t b0[3], b1[3];
+            for (int a = 0; a < 3; ++a) {
+                b0[a] = std::max<int64_t>(0, (int64_t)std::floor((c[a] - d->radius) / h) - 1 - g->lo[a]);
+                b1[a] = std::min<int64_t>(g->L[a] - 1, (int64_t)std::ceil((c[a] + d->radius) / h) + 1 - g->lo[a]);
             }
+            for (int64_t k = b0[2]; k <= b1[2]; ++k) {
+                const double dz = (double)(k + g->lo[2]) * h - c[2];
+                for (int64_t j = b0[1]; j <= b1[1]; ++j) {
+                    const double dy = (double)(j + g->lo[1]) * h - c[1];
+                    for (int64_t i = b0[0]; i <= b1[0]; ++i) {
+                        const double dx = (double)(i + g->lo[0]) * h - c[0];
+                        if ((dx * dx + dy * dy) + dz * dz <= r2) inside[(k * L1 + j) * L0 + i] = 1;
+                    }
+                }
+            }
+        }
+    } else {
+        for (int64_t k = 0; k < L2; ++k)
+            for (int64_t j = 0; j < L1; ++j)
+                for (int64_t i = 0; i < L0; ++i) {
+                    const int64_t x = i + g->lo[0], y = j + g->lo[1], z = k + g->lo[2];
+                    bool in;
+                    if (d->kind == RS_GRID_SPHERE) in = x * x + y * y + z * z <= Q;
+                    else in = x >= 0 && x < ext[0] && y >= 0 && y < ext[1] && z >= 0 && z < ext[2];
+                    inside[(k * L1 + j) * L0 + i] = in;
+                }
+    }
     auto is_in = [&](int64_t i, int64_t j, int64_t k) -> bool {
         if (i < 0 || j < 0 || k < 0 || i >= L0 || j >= L1 || k >= L2) return false;
         return inside[(k * L1 + j) * L0 + i];

@@ -100,6 +100,7 @@ struct rs_grid {
     double h = 0;
     int n = 0;
     double radius = 0;
+    std::vector<double> centres;     // [natoms][3] sphere centres (union grids)
     int brick[3] = {4, 4, 4};
     int64_t lo[3] = {0, 0, 0};   // integer coordinate of lattice origin
     int64_t L[3] = {0, 0, 0};    // lattice dims

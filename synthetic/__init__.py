@@ -34,8 +34,9 @@ class Workload:
     """Description of one synthetic system.
 
     grid_kind: "box" (zero Dirichlet outside an n^3 cell-centred box),
-               "periodic" (n^3 periodic box) or "sphere" (all points within
-               ``radius`` of the centre).
+               "periodic" (n^3 periodic box), "sphere" (all points within
+               ``radius`` of the centre) or "union" (all points within
+               ``radius`` of some atom: the molecular grid).
     """
     name: str
     grid_kind: str
@@ -63,7 +64,9 @@ class Workload:
 
 # The workloads, by name: a harmonic box, a sphere in FP64, the same sphere
 # in FP32 / split precision, a periodic box for the learned preconditioner,
-# and a large sphere with a cage of atoms.
+# a large sphere with a cage of atoms, and a molecular grid (union of 5.5
+# bohr spheres at h 0.41, the paper's grid parameters) around a 60-atom
+# cage.
 WORKLOADS = {w.name: w for w in (
     Workload("box32_harmonic", "box", 0.3, n=32, nstates=8, block=8, seed=1,
              potential="harmonic"),
@@ -75,6 +78,9 @@ WORKLOADS = {w.name: w for w in (
              block=32, seed=4, nat=32, atom_layout="box"),
     Workload("sphere_r18_h0.18_cage60", "sphere", 0.18, radius=18.0,
              nstates=240, block=64, seed=5, nat=60, atom_layout="cage",
+             atom_radius=6.7),
+    Workload("union_cage60_r5.5_h0.41", "union", 0.41, radius=5.5,
+             nstates=128, block=32, seed=6, nat=60, atom_layout="cage",
              atom_radius=6.7),
 )}
 

@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Writes the reference eigenvalues of a sphere workload into tests/golden/.
+"""Writes the reference eigenvalues of a workload into tests/golden/.
 
 The stored values are the lowest ``nev`` eigenvalues of the FP64 operator
 H = T + V + V_nl of the named synthetic workload (Sec. 5 and eq. (6)), computed
@@ -7,7 +7,7 @@ by scipy's LOBPCG on the oracle's operator (``oracle.lobpcg_ref``).  Only
 ``oracle/`` and ``synthetic/`` are used.  One line per eigenvalue: index,
 eigenvalue (Ha), residual norm |H v - lambda v| of the normalised vector.
 
-Usage: python tests/golden/make_sphere_eigs.py [--workload sphere_r12_h0.2]
+Usage: python tests/golden/make_eigs.py [--workload sphere_r12_h0.2]
            [--nev 128] [--nguard 32] [--tol 1e-7] [--maxiter 400]
 """
 from __future__ import annotations
@@ -50,7 +50,7 @@ def main():
                 f"{a.nev + a.nguard} vectors,\n")
         f.write("# H applied by the C oracle, preconditioner (T + 1)^-1 on an enclosing periodic box "
                 "(oracle/lobpcg_ref.py);\n")
-        f.write(f"# written by tests/golden/make_sphere_eigs.py, tol {a.tol:g}, {el:.0f} s.\n")
+        f.write(f"# written by tests/golden/make_eigs.py, tol {a.tol:g}, {el:.0f} s.\n")
         f.write("# columns: index, eigenvalue, residual norm of the normalised eigenvector\n")
         for k in range(a.nev):
             f.write(f"{k} {lam[k]:.15e} {res[k]:.3e}\n")

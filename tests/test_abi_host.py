@@ -70,11 +70,38 @@ def test_index_map_bit_exact(args):
     assert tuple(g.lo) == tuple(og.lo)
 
 
+@pytest.mark.parametrize("brick", [(4, 4, 4), (2, 3, 5), (8, 8, 8), (128, 128, 128)])
+def test_union_index_map_bit_exact(brick):
+    """The molecular grid of the 60-atom cage workload (union of 5.5-bohr
+    spheres at h 0.41) in several sub-grid shapes, the largest being the
+    standard (lexicographic) order."""
+    w = synthetic.WORKLOADS["union_cage60_r5.5_h0.41"]
+    og = ogrid.grid_for(w, brick=brick)
+    g = rsd.Grid.for_workload(w, host_only=True, brick=brick)
+    assert g.np == og.np and g.nbnd == og.nbnd
+    ex = g.export()
+    assert np.array_equal(ex["inner"], og.inner)
+    assert np.array_equal(ex["boundary"], og.boundary.reshape(-1, 3))
+    assert np.array_equal(ex["brick_map"], og.brick_map)
+    assert np.array_equal(ex["xyz"], og.xyz)
+    assert tuple(g.lo) == tuple(og.lo)
+
+
+def test_union_grid_bad_arguments():
+    for kw in (dict(centres=None), dict(centres=np.array([[0.0, 0.0, np.nan]])),
+               dict(centres=np.zeros((2, 3)), radius=0.0)):
+        kw = dict(dict(radius=2.0), **kw)
+        with pytest.raises(_abi.RsError) as e:
+            rsd.Grid("union", 0.3, host_only=True, **kw)
+        assert e.value.code == _abi.RS_EINVAL
+
+
 @pytest.mark.parametrize("cfg", [
     dict(name="sphere_r12_h0.2", radius=4.0, nat=5, atom_radius=2.5),
     dict(name="sphere_r12_h0.2"),
     dict(name="periodic96_h0.25", n=24, nat=6),
     dict(name="sphere_r18_h0.18_cage60", radius=9.0, nat=60, atom_radius=6.7, rc=1.2),
+    dict(name="union_cage60_r5.5_h0.41"),
 ])
 def test_projector_sets_match_oracle(cfg):
     cfg = dict(cfg)

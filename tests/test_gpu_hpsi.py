@@ -194,3 +194,43 @@ def test_bad_block_size_rejected():
     st = rsd.lib().rs_hpsi_block(g.handle, nl.handle, rsd._dev(v, "v"), rsd._dev(t, "psi"), rsd._dev(out, "hpsi"),
                                  1, 3, rsd.RS_F64, None)
     assert st == rsd._abi.RS_EINVAL
+
+
+UNION_SMALL = synthetic.make_workload("union_cage60_r5.5_h0.41", nat=6, atom_radius=2.0, radius=2.5, h=0.3)
+
+
+@pytest.mark.parametrize("dtype,B,tol", [(np.float64, 16, 1e-12), (np.float64, 32, 1e-12), (np.float64, 8, 1e-12),
+                                         (np.float32, 32, 1e-5), (np.float32, 4, 1e-5)])
+def test_hpsi_union_of_spheres(dtype, B, tol):
+    """The molecular grid (union of spheres around 6 atoms on a small cage):
+    FP64 blocks of 16 and 32 run the z-marching kernel over the irregular
+    brick columns, B = 8 and FP32 the per-brick kernel."""
+    og, H, g, nl = _system(UNION_SMALL)
+    assert og.kind == "union" and g.np == og.np
+    psi = _states(UNION_SMALL, 2 * B, og.np, dtype)
+    v = H.vloc.astype(dtype)
+    Hq = hamiltonian.Hamiltonian(og, v.astype(np.float64), H.proj)
+    got = _gpu_hpsi(g, nl, v, psi, B, dtype)
+    assert _relerr(got, Hq.apply(psi.astype(np.float64))) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+def test_full_size_union_sampled(dtype, tol):
+    """The 60-atom molecular grid (103k points, h 0.41, 5.5-bohr spheres),
+    all 128 states in blocks of 32, at sampled points."""
+    w = synthetic.WORKLOADS["union_cage60_r5.5_h0.41"]
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=128)
+    psi = _states(w, 128, og.np, dtype)
+    v = H.vloc.astype(dtype)
+    got = _gpu_hpsi(g, nl, v, psi, 32, dtype)
+    x64 = psi.astype(np.float64)
+    rng = np.random.default_rng(13)
+    pts = rng.choice(og.np, 400, replace=False)
+    sph = np.concatenate(H.proj.idx)
+    pts = np.unique(np.concatenate([pts, rng.choice(sph, 200, replace=False)]))
+    want = stencil.apply_local_at(og, v.astype(np.float64), x64, pts)
+    P = kb.project(H.proj, x64)
+    want += kb.apply_projections(H.proj, P, og.np)[:, pts]
+    assert _relerr(got[:, pts], want) < tol

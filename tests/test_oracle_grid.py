@@ -153,3 +153,52 @@ def test_brick_map_numbering():
     b = u // 4
     bid = (b[:, 2] * g.nb[1] + b[:, 1]) * g.nb[0] + b[:, 0]
     assert np.all(np.diff(bid) >= 0)
+
+
+def _union_brute(centres, radius, h, brick, M=4):
+    """Union-of-spheres grid by plain loops: every lattice point near any
+    sphere, inside iff within radius of some centre (Python floats, the
+    same rounding order), boundary by the one-axis reach rule, sub-grid
+    order."""
+    c = [tuple(map(float, x)) for x in centres]
+    lo = [int(np.floor((min(p[a] for p in c) - radius) / h)) - M for a in range(3)]
+    hi = [int(np.ceil((max(p[a] for p in c) + radius) / h)) + M for a in range(3)]
+
+    def inside(p):
+        for X, Y, Z in c:
+            dx, dy, dz = p[0] * h - X, p[1] * h - Y, p[2] * h - Z
+            if (dx * dx + dy * dy) + dz * dz <= radius * radius:
+                return True
+        return False
+
+    pts = [(i, j, k) for k in range(lo[2], hi[2] + 1) for j in range(lo[1], hi[1] + 1)
+           for i in range(lo[0], hi[0] + 1)]
+    ins = {p for p in pts if inside(p)}
+    bnd = [p for p in pts if p not in ins and any(
+        tuple(p[d] + (s * m if d == a else 0) for d in range(3)) in ins
+        for a in range(3) for m in range(1, M + 1) for s in (1, -1))]
+
+    def key(p):
+        u = [p[d] - lo[d] for d in range(3)]
+        b = [u[d] // brick[d] for d in range(3)]
+        s = [u[d] % brick[d] for d in range(3)]
+        return (b[2], b[1], b[0], s[2], s[1], s[0])
+
+    return sorted(ins, key=key), sorted(bnd, key=key)
+
+
+@pytest.mark.parametrize("brick", [(4, 4, 4), (2, 3, 5)])
+def test_union_of_spheres_bruteforce(brick):
+    """The molecular grid (Sec. 2, Fig. "struct"): three overlapping and one
+    separate sphere around off-lattice centres."""
+    centres = np.array([[0.13, -0.41, 0.27], [1.37, 0.52, -0.33], [0.61, 1.44, 0.95], [4.9, -2.2, 0.4]])
+    g = grid.build_grid("union", 0.45, radius=1.6, brick=brick, centres=centres)
+    inner, bnd = _union_brute(centres, 1.6, 0.45, brick)
+    assert [tuple(p) for p in g.inner.tolist()] == inner
+    assert [tuple(p) for p in g.boundary.tolist()] == bnd
+    # each atom's sphere is inside the grid, and the union has fewer points
+    # than the spheres' separate counts (they overlap)
+    d2 = ((g.xyz[:, None, :] - centres[None]) ** 2).sum(-1)
+    assert np.all(d2.min(axis=1) <= 1.6 ** 2 + 1e-12)
+    per = [(((g.xyz - c) ** 2).sum(-1) <= 1.6 ** 2).sum() for c in centres]
+    assert g.np < sum(per)
