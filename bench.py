@@ -15,7 +15,8 @@ states, with inputs resident in HBM.  Prints one JSON line:
   cpu_baseline = the FP64 C/OpenMP oracle on the host cores (bounded sample).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-eig] [--no-cpu] [--no-fp32]
+                       [--no-eig] [--no-cpu] [--no-fp32] [--no-learned] [--no-cage]
+       python bench.py --ordering-study
 """
 from __future__ import annotations
 
@@ -52,7 +53,7 @@ def setup(w, dtype, B):
     v = synthetic.potential_for(w, xyz, atoms)
     nl = None
     if atoms is not None:
-        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=w.nstates)
+        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=-(-w.nstates // B) * B)
     rng = synthetic.rng_after_atoms(w)
     npdt = np.float64 if dtype == "f64" else np.float32
     psi = synthetic.draw_states(rng, w.nstates, g.np).astype(npdt)
@@ -254,15 +255,15 @@ def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every
     g = rsd.Grid.for_workload(w)
     atoms = synthetic.draw_atoms(w) if w.nat else None
     v = synthetic.potential_for(w, g.xyz(), atoms)
-    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=w.nstates) if atoms is not None else None
+    nl = (rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=-(-w.nstates // B) * B)
+          if atoms is not None else None)
     npdt = np.float64 if dtype == "f64" else np.float32
     psi = synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np).astype(npdt)
     tp = torch.from_numpy(rsd.to_blocks(psi, B)).cuda()
     del psi
     tv = torch.from_numpy(v.astype(npdt)).cuda()
-    ctx = rsd.Context(g, w.nstates)
-    ctx.orthonormalize(tp)
     solver = rsd.Eigensolver(g, nl, tv, w.nstates, B, tol=tol_res, block_stop=True)
+    solver.orthonormalize(tp)          # padding states (B not dividing N) stay zero
     keep = w.nstates - nbuf
     times, eigs, t_hit, k_hit = [], [], None, None
     elapsed = 0.0
@@ -281,7 +282,7 @@ def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every
         if np.all(res[:keep] < tol_res) or (stop_at_hit and t_hit is not None):
             break
     step_ms = 1e3 * (times[-1] - times[min(4, len(times) - 1)]) / max(1, len(times) - 1 - min(4, len(times) - 1))
-    del solver, ctx, tp
+    del solver, tp
     torch.cuda.empty_cache()
     return dict(steps=len(times), eig=eigs[-1], eigs=eigs, times=times, t_hit=t_hit, k_hit=k_hit,
                 ms_per_step=step_ms, keep=keep, final_max_res=float(res[:keep].max()))
@@ -436,6 +437,71 @@ def cage_compare(max_steps=300):
     }
 
 
+def ordering_study(steps=10):
+    """Sec. 5.1 (Figs. "locality", "cache", "laplacian") on the molecular
+    grid: (1) the FP64 C/OpenMP oracle's H psi throughput on the host cores
+    for the standard (lexicographic) order and sub-grid orders of several
+    brick sizes, all 128 states in blocks of 32, plus block sizes 1..64 in
+    4x4x4 order; (2) the GPU's H psi throughput (FP64 and FP32) for block
+    sizes 1..64 (the kernels use 4x4x4 bricks)."""
+    import torch
+    import paper_1306_2953_amd as rsd
+    from oracle import cpu_hpsi, grid as ogrid, hamiltonian
+    w = synthetic.WORKLOADS["union_cage60_r5.5_h0.41"]
+    cpu_hpsi.build()
+    atoms = synthetic.draw_atoms(w)
+    out = {"workload": w.name, "states": w.nstates, "cpu_threads": cpu_hpsi.threads(),
+           "cpu": cpu_hpsi.cpu_model(), "unit": "grid-pt*states/s"}
+
+    def cpu_rate(og, B, budget=3.0):
+        v = synthetic.potential_for(w, og.xyz, atoms)
+        from oracle import kb
+        H = hamiltonian.Hamiltonian(og, v, kb.build_projectors(og, atoms.pos, atoms.D, w.rc, w.sigma))
+        ch = cpu_hpsi.CpuHamiltonian(H)
+        psi = synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, og.np)
+        blk = np.ascontiguousarray(psi.reshape(w.nstates // B, B, og.np).transpose(0, 2, 1))
+        ch.hpsi_blocks(blk)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            ch.hpsi_blocks(blk)
+            reps += 1
+        return og.np * w.nstates * reps / (time.perf_counter() - t0)
+
+    orders = {}
+    L = None
+    for name, brick in (("standard", None), ("bricks 2x2x2", (2, 2, 2)), ("bricks 4x4x4", (4, 4, 4)),
+                        ("bricks 8x8x8", (8, 8, 8)), ("bricks 16x16x16", (16, 16, 16))):
+        if brick is None:
+            L = int(ogrid.grid_for(w).L.max())
+            brick = (L, L, L)
+        og = ogrid.grid_for(w, brick=brick)
+        orders[name] = cpu_rate(og, 32)
+        log(f"ordering study: cpu {name}: {orders[name]:.3e}")
+    out["cpu_order_B32"] = orders
+    og = ogrid.grid_for(w)
+    out["cpu_block_size_4x4x4"] = {B: cpu_rate(og, B) for B in (1, 4, 16, 32, 64)}
+    log(f"ordering study: cpu block sizes {out['cpu_block_size_4x4x4']}")
+    g = rsd.Grid.for_workload(w)
+    v = synthetic.potential_for(w, g.xyz(), atoms)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=w.nstates)
+    gpu = {}
+    for dt, npdt in (("f64", np.float64), ("f32", np.float32)):
+        tv = torch.from_numpy(v.astype(npdt)).cuda()
+        psi = synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np).astype(npdt)
+        rates = {}
+        for B in (1, 2, 4, 8, 16, 32, 64):
+            tp = torch.from_numpy(rsd.to_blocks(psi, B)).cuda()
+            th = torch.empty_like(tp)
+            f = lambda: rsd.hpsi_block(g, nl, tv, tp, th)
+            f()
+            t = time_calls(f, steps, torch.cuda.current_stream())
+            rates[B] = g.np * w.nstates / t
+        gpu[dt] = rates
+        log(f"ordering study: gpu {dt} block sizes {rates}")
+    out["gpu_block_size"] = gpu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,8 +513,14 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--ordering-study", action="store_true",
+                    help="point-ordering and block-size study on the molecular grid (host oracle and GPU); "
+                         "prints one JSON line")
     ap.add_argument("--no-cage", action="store_true",
-                    help="skip the large-sphere lines (FP32 H psi throughput and the eigensolve comparison)")
+                    help="skip the large-sphere FP32 H psi throughput line")
+    ap.add_argument("--cage-eig", type=int, default=0, metavar="STEPS",
+                    help="also run the large-sphere eigensolve comparison (FP64 reference run of up to STEPS "
+                         "steps, about 0.25 s each, then the FP32 solve timed against it)")
     ap.add_argument("--profile-eig", type=int, default=0, metavar="K",
                     help="for kernel-trace runs: K eigensolver steps of the FP64 sphere and of "
                          "its FP32 split-precision form from the seeded start; prints step times")
@@ -471,6 +543,9 @@ def main():
             wk = synthetic.WORKLOADS[name]
             r = eigensolve_run(wk, dt, wk.block, a.profile_eig, 0.0, log_every=1)
             log(f"{wk.name} {dt}: step times {np.diff([0.0] + r['times'])}")
+        return
+    if a.ordering_study:
+        print(json.dumps(ordering_study(a.steps)), flush=True)
         return
     if a.traffic_record:
         traffic_record(w, dtype, *a.traffic_record)
@@ -500,8 +575,8 @@ def main():
         eig = eigensolve_compare()
         log(f"eigensolve: {eig}")
     cage = None
-    if primary and not a.no_eig and not a.no_cage:
-        cage = cage_compare()
+    if primary and a.cage_eig > 0:
+        cage = cage_compare(a.cage_eig)
         log(f"cage eigensolve: {cage}")
     lrn = None
     if primary and not a.no_learned:
