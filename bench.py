@@ -288,12 +288,12 @@ def eigensolve_run(w, dtype, B, max_steps, tol_res, ref=None, nbuf=16, log_every
                 ms_per_step=step_ms, keep=keep, final_max_res=float(res[:keep].max()))
 
 
-def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
+def learned_compare(w, max_steps=200, train_iters=30000, nbuf=16):
     """FP32 solve of the periodic workload with the trained network (a
     second direction next to the filter's in every trial step) against the
     same solve with the filter alone, from the same seeded start.  The
-    network is trained first on the GPU (30 recorded filter steps, CG
-    targets, energy-norm loss).  Reference eigenvalues: the golden LOBPCG
+    network is trained first on the GPU (one crop per state from each of 60
+    recorded filter steps, CG targets, energy-norm loss).  Reference eigenvalues: the golden LOBPCG
     values when present, else an FP64 filter solve run to residual 1e-6 on
     the lowest N - nbuf states."""
     import torch
@@ -324,7 +324,7 @@ def learned_compare(w, max_steps=200, train_iters=20000, nbuf=16):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rec = rsd.Eigensolver(g, nl, tv, w.nstates, w.block, tol=1e-5, record=True)
-    pairs = learned.collect_pairs(g, rec, psi0.clone(), net, steps=30, crops_per_state=2, crop=16, rng=rng,
+    pairs = learned.collect_pairs(g, rec, psi0.clone(), net, steps=60, crops_per_state=1, crop=16, rng=rng,
                                   cg_tol=1e-5)
     del rec
     t_collect = time.perf_counter() - t0
@@ -435,6 +435,28 @@ def cage_compare(max_steps=300):
         "fp32_split_filter": {"time_s": r32["t_hit"], "steps": r32["k_hit"], "ms_per_step": r32["ms_per_step"],
                               "final_max_eig_error_ha": float(np.max(np.abs(r32["eig"][:keep] - ref[:keep])))},
     }
+
+
+def hartree_rate(w, steps=10):
+    """Hartree potential (Sec. 7) of a Gaussian density on the workload's grid:
+    time per solve, the FFT box, and the bytes the six 1-D FFT passes move
+    (each reads and writes the complex FP64 box once)."""
+    import torch
+    import paper_1306_2953_amd as rsd
+    g = rsd.Grid.for_workload(w)
+    xyz = g.xyz()
+    r2 = np.sum(xyz * xyz, axis=1)
+    rho = torch.from_numpy((2 * np.pi) ** -1.5 * np.exp(-r2 / 2.0)).cuda()
+    ps = rsd.Poisson(g)
+    out = torch.empty_like(rho)
+    f = lambda: ps.solve(rho, out)
+    for _ in range(2):
+        f()
+    t = time_calls(f, steps, torch.cuda.current_stream())
+    fft_bytes = 6 * 2 * 16 * ps.nbox ** 3
+    return {"workload": w.name, "grid_points": g.np, "fft_box": ps.nbox, "cutoff_radius_bohr": ps.rc,
+            "ms_per_solve": t * 1e3, "fft_pass_bytes": fft_bytes,
+            "fft_pass_bytes_over_solve_time_gbs": fft_bytes / t / 1e9}
 
 
 def ordering_study(steps=10):
@@ -570,6 +592,9 @@ def main():
         extra[w5.name] = {k: r5[k] for k in ("ptstates_per_s", "gflops", "t_step", "t_kernel", "achieved_gbs",
                                              "frac", "np", "N", "B", "nblk")}
         extra[w5.name]["note"] = "240 states in 4 blocks of 64 (16 zero padding states, not counted)"
+    if primary:
+        extra["hartree"] = hartree_rate(w)
+        log(f"hartree: {extra['hartree']}")
     eig = None
     if primary and not a.no_eig:
         eig = eigensolve_compare()

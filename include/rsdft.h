@@ -259,6 +259,32 @@ rs_status rs_orthonormalize_block(rs_ctx *c, void *psi, int32_t nblk, int32_t B,
 rs_status rs_subspace_diag(rs_ctx *c, void *psi, void *hpsi, double *eig, int32_t nblk,
                            int32_t B, int32_t dtype, int32_t prec, void *stream);
 
+/* --------------------------------------------- Hartree potential, Sec. 7
+ * Eq. (5): V_H solves nabla^2 V = -4 pi n; for a finite system V(r) =
+ * int n(r') / |r - r'| d^3r'.  The density on the grid's inner points is
+ * placed in an N^3 box (zeros elsewhere), transformed by a 3-D FFT,
+ * multiplied by the Coulomb interaction cut off at R_c,
+ *     v(k) = 4 pi / k^2 (1 - cos(k R_c)),  v(0) = 2 pi R_c^2,
+ * transformed back and read out at the inner points.  R_c = twice the
+ * largest distance of an inner point from the centre of their bounding box
+ * (so it bounds every pair distance); N = the smallest power of two with
+ * N > (extent - 1) + R_c / h on every axis (the box then keeps every
+ * periodic image of the density more than R_c from the domain), at least
+ * 16 and at most 512 (RS_ENOTSUP beyond).  FP64 throughout.  Finite grids
+ * only (RS_EINVAL for periodic ones).  The handle owns the box (16 N^3
+ * bytes) and the point table; it holds a pointer to the grid, which must
+ * outlive it. */
+typedef struct rs_poisson rs_poisson;
+rs_status rs_poisson_create(const rs_grid *g, rs_poisson **out);
+void rs_poisson_destroy(rs_poisson *p);
+/* The box edge N and R_c (bohr) chosen at creation (HOST outputs, may be
+ * NULL). */
+rs_status rs_poisson_info(const rs_poisson *p, int32_t *nbox, double *rc);
+/* vh[p] = V_H at inner point p for the density rho[p]; rho, vh DEVICE
+ * double [np], distinct.  Calls on one handle must not overlap in time (one
+ * box).  Asynchronous. */
+rs_status rs_poisson_solve(rs_poisson *p, const double *rho, double *vh, void *stream);
+
 /* ------------------------------------------------- eigensolver, Sec. 3
  * RMM-DIIS with the filter preconditioner and the block stopping rule of
  * Sec. 9.  One rs_eigensolve_step:

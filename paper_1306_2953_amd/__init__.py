@@ -251,6 +251,40 @@ def overlap_noalloc(grid: Grid, x, y, S, prec=None, stream=None):
     return S
 
 
+class Poisson:
+    """Hartree potential of a density on a finite grid by FFT on an enlarged
+    box with the cut-off Coulomb kernel (rs_poisson)."""
+
+    def __init__(self, grid: Grid):
+        self.grid = grid
+        self._h = ctypes.c_void_p()
+        check(lib().rs_poisson_create(grid.handle, ctypes.byref(self._h)))
+        n, rc = ctypes.c_int32(), ctypes.c_double()
+        check(lib().rs_poisson_info(self._h, ctypes.byref(n), ctypes.byref(rc)))
+        self.nbox, self.rc = n.value, rc.value
+
+    def solve(self, rho, out=None, stream=None):
+        """V_H [np] (float64, on rho's device) for the density rho [np]."""
+        torch = _torch()
+        _check(rho, "rho", dtype=torch.float64, numel=self.grid.np)
+        if not rho.is_cuda:
+            raise ValueError("rho must be a device tensor")
+        if out is None:
+            out = torch.empty_like(rho)
+        _check(out, "out", like=rho)
+        if out.data_ptr() == rho.data_ptr():
+            raise ValueError("out must not alias rho")
+        check(lib().rs_poisson_solve(self._h, _dev(rho, "rho"), _dev(out, "out"), _stream(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_poisson_destroy(h)
+            self._h = None
+
+
 class Context:
     """Workspaces of the orthogonalisation / subspace stage (rs_ctx)."""
 

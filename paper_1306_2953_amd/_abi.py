@@ -84,6 +84,10 @@ SIGNATURES = {
     "rs_cnn_precondition": (ctypes.c_int, [P, P, P, P, P, I32, I32, I32, P]),
     "rs_cnn_box": (ctypes.c_int, [P, P, PI32]),
     "rs_cnn_crops": (ctypes.c_int, [P, P, P, P, I32, I32, I32, I32, P, PI32, P, P, P]),
+    "rs_poisson_create": (ctypes.c_int, [P, ctypes.POINTER(P)]),
+    "rs_poisson_destroy": (None, [P]),
+    "rs_poisson_info": (ctypes.c_int, [P, PI32, PF64]),
+    "rs_poisson_solve": (ctypes.c_int, [P, P, P, P]),
     "rs_shifted_solve": (ctypes.c_int, [P, P, P, P, I32, I32, I32, F64, I32, PI32, P]),
 }
 
