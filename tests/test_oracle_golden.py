@@ -21,7 +21,7 @@ def _load(name):
     return idx, lam, res
 
 
-@pytest.mark.parametrize("name,n", [("sphere_r12_h0.2", 128)])
+@pytest.mark.parametrize("name,n", [("sphere_r12_h0.2", 128), ("periodic96_h0.25", 256)])
 def test_golden_eigenvalues_consistent(name, n):
     idx, lam, res = _load(name)
     assert np.array_equal(idx, np.arange(n))
