@@ -348,6 +348,45 @@ rs_status rs_eigensolve_step(rs_solver *s, void *psi, double *eig, double *resno
  * the states are linearly dependent. */
 rs_status rs_eigensolve_orthonormalize(rs_solver *s, void *psi, void *stream);
 
+/* ------------------------------------------------- SCF loop, Sec. 3
+ * Fig. "groundstate": per iteration V_eff = V_ion + V_H[n_in] + V_xc[n_in]
+ * (V_H by the FFT solve above; V_xc the local density approximation: Dirac
+ * exchange and the Perdew-Zunger (1981) correlation, unpolarised), then
+ * eig_steps rs_eigensolve_step calls on the states with that potential,
+ * then n_out = 2 sum_{k < nocc} psi_k^2 (eq. 1b; closed shell, real
+ * states) and F = n_out - n_in, and Broyden's second method in Anderson's
+ * form: with the differences dn_j, dF_j of the last `history` iterations,
+ * gamma solves (dF_i . dF_j) gamma = (dF_i . F) (h^3-weighted; gamma = 0 if
+ * singular) and n_in <- n_in + mix F - sum_j gamma_j (dn_j + mix dF_j).
+ * Densities, potentials and the history are FP64; the states are dtype. */
+typedef struct {
+    int32_t nocc;         /* occupied states (2 electrons each), 1..nstates */
+    int32_t eig_steps;    /* eigensolver steps per SCF iteration, 1..100    */
+    int32_t history;      /* mixing history length, 0..8                    */
+    double  mix;          /* mixing weight, (0, 1]                          */
+    rs_solver_opts solver;  /* options of the eigensolver it runs          */
+} rs_scf_opts;
+typedef struct rs_scf rs_scf;
+/* vion: DEVICE double [np], copied.  Creates its eigensolver (whose local
+ * potential is the handle's V_eff) and its Hartree solver; finite grids
+ * only. */
+rs_status rs_scf_create(const rs_grid *g, const rs_nl *nl, const double *vion, int32_t nstates,
+                        int32_t B, int32_t dtype, const rs_scf_opts *opts, rs_scf **out);
+void rs_scf_destroy(rs_scf *s);
+/* Orthonormalises psi (the eigensolver's layout) and takes its density as
+ * the first n_in.  Synchronises. */
+rs_status rs_scf_start(rs_scf *s, void *psi, void *stream);
+/* One SCF iteration on psi (updated in place).  eig, resnorm: HOST double
+ * [nstates] (may be NULL), the last eigensolver step's outputs; dens_res:
+ * HOST, ||n_out - n_in|| = (h^3 sum F^2)^(1/2) of this iteration (before
+ * mixing).  Synchronises. */
+rs_status rs_scf_iterate(rs_scf *s, void *psi, double *eig, double *resnorm, double *dens_res,
+                         void *stream);
+/* Copies of the current input density (after the last mixing) and of the
+ * last output density into DEVICE double [np] buffers (either may be
+ * NULL).  Asynchronous. */
+rs_status rs_scf_density(const rs_scf *s, double *n_in, double *n_out, void *stream);
+
 /* ------------------------------------------- learned preconditioner
  * Not from the paper: its RMM-DIIS step (Sec. 3) leaves the preconditioner
  * open and uses a filter; this replaces the filter by a small network

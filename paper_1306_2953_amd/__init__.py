@@ -394,6 +394,63 @@ class Context:
         return ev
 
 
+class Scf:
+    """The self-consistent field loop (rs_scf): effective potential from the
+    density (Hartree by FFT, LDA), eig_steps eigensolver steps, output
+    density, Broyden/Anderson mixing."""
+
+    def __init__(self, grid: Grid, nl: Optional[NonLocal], vion, nstates: int, B: int, nocc: int,
+                 dtype=None, eig_steps: int = 3, mix: float = 0.3, history: int = 5,
+                 m: int = 3, alpha: float = 0.6, tol: float = 1e-6, block_stop: bool = True):
+        torch = _torch()
+        _check(vion, "vion", dtype=torch.float64, numel=grid.np)
+        if not vion.is_cuda:
+            raise ValueError("vion must be a device tensor")
+        self.grid, self.nstates, self.B = grid, nstates, B
+        self.nblk = -(-nstates // B)
+        self.dtype = torch.float64 if dtype is None else dtype
+        o = _abi.ScfOpts()
+        o.nocc, o.eig_steps, o.history, o.mix = int(nocc), int(eig_steps), int(history), float(mix)
+        o.solver.m, o.solver.alpha, o.solver.tol = int(m), float(alpha), float(tol)
+        o.solver.block_stop, o.solver.record, o.solver.rr_sweeps = int(block_stop), 0, 0
+        code = RS_F64 if self.dtype == torch.float64 else RS_F32
+        self._h = ctypes.c_void_p()
+        check(lib().rs_scf_create(grid.handle, nl.handle if nl is not None else None, _dev(vion, "vion"),
+                                  int(nstates), int(B), code, ctypes.byref(o), ctypes.byref(self._h)))
+
+    def _own(self, psi):
+        _check(psi, "psi", shape=(self.nblk, self.grid.np, self.B), dtype=self.dtype)
+
+    def start(self, psi, stream=None):
+        self._own(psi)
+        check(lib().rs_scf_start(self._h, _dev(psi, "psi"), _stream(stream)))
+
+    def iterate(self, psi, stream=None):
+        """One SCF iteration in place; returns (eig, resnorm, density residual)."""
+        self._own(psi)
+        eig = np.empty(self.nstates)
+        res = np.empty(self.nstates)
+        dr = ctypes.c_double(0.0)
+        check(lib().rs_scf_iterate(self._h, _dev(psi, "psi"), eig.ctypes.data_as(_abi.PF64),
+                                   res.ctypes.data_as(_abi.PF64), ctypes.byref(dr), _stream(stream)))
+        return eig, res, dr.value
+
+    def densities(self, stream=None):
+        """(n_in, n_out) device float64 [np] copies."""
+        torch = _torch()
+        a = torch.empty(self.grid.np, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        check(lib().rs_scf_density(self._h, _dev(a, "n_in"), _dev(b, "n_out"), _stream(stream)))
+        return a, b
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(_abi, "_lib", None) if _abi is not None else None
+        if h and L is not None:
+            L.rs_scf_destroy(h)
+            self._h = None
+
+
 class Eigensolver:
     """RMM-DIIS eigensolver over the states of one grid (rs_solver)."""
 

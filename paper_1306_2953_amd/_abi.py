@@ -32,6 +32,10 @@ class SolverOpts(ctypes.Structure):
                 ("rr_sweeps", I32)]
 
 
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("nocc", I32), ("eig_steps", I32), ("history", I32), ("mix", F64), ("solver", SolverOpts)]
+
+
 class SolverStats(ctypes.Structure):
     _fields_ = [("steps", I32), ("rr_sweeps", I32), ("frozen_blocks", I32), ("net_states", I32)]
 
@@ -88,6 +92,11 @@ SIGNATURES = {
     "rs_poisson_destroy": (None, [P]),
     "rs_poisson_info": (ctypes.c_int, [P, PI32, PF64]),
     "rs_poisson_solve": (ctypes.c_int, [P, P, P, P]),
+    "rs_scf_create": (ctypes.c_int, [P, P, P, I32, I32, I32, P, ctypes.POINTER(P)]),
+    "rs_scf_destroy": (None, [P]),
+    "rs_scf_start": (ctypes.c_int, [P, P, P]),
+    "rs_scf_iterate": (ctypes.c_int, [P, P, PF64, PF64, PF64, P]),
+    "rs_scf_density": (ctypes.c_int, [P, P, P, P]),
     "rs_shifted_solve": (ctypes.c_int, [P, P, P, P, I32, I32, I32, F64, I32, PI32, P]),
 }
 
