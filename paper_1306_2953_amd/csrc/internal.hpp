@@ -81,7 +81,7 @@ static_assert(sizeof(BrickRec) == 40, "BrickRec layout");
 // brick has mask 0; id is the brick's number where the chunk owns (writes)
 // it, -1 otherwise (neighbours, and periodic images of bricks owned by
 // another tile).
-constexpr int kMarchCZ = 9;
+constexpr int kMarchCZ = 9;    // 36-layer bands measured within 2 % in time, with 10 % more fetched bytes
 struct MarchBrick {
     uint64_t mask;
     int32_t start;
