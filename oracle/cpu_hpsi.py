@@ -72,6 +72,8 @@ class CpuHamiltonian:
         self.vloc = np.ascontiguousarray(H.vloc, dtype=np.float64)
         ps = H.proj
         if ps is not None and ps.nat:
+            if ps.nproj != 4:
+                raise ValueError("the C kernel takes the s and p projectors (lmax 1) only")
             self.nat = ps.nat
             lens = [len(i) for i in ps.idx]
             self.sph_ptr = np.zeros(self.nat + 1, dtype=np.int64)

@@ -31,8 +31,11 @@ def dots(f: np.ndarray, g: np.ndarray, dv: float) -> np.ndarray:
     return dv * np.einsum("kp,kp->k", f, g)
 
 
-def overlap(psi: np.ndarray, dv: float) -> np.ndarray:
-    return dv * (psi @ psi.T)
+def overlap(psi: np.ndarray, dv: float, other: np.ndarray = None) -> np.ndarray:
+    """Eq. (7): S[j, k] = h^3 sum_p conj(psi_j(p)) other_k(p) (other = psi by
+    default), for state-major [N, np] arrays, real or complex."""
+    y = psi if other is None else other
+    return dv * (np.conj(psi) @ y.T)
 
 
 def cholesky_upper(S: np.ndarray) -> np.ndarray:

@@ -104,3 +104,124 @@ def test_periodic_minimum_image():
     G0 = ps.gamma[0].T @ ps.gamma[0]
     G1 = ps.gamma[1].T @ ps.gamma[1]
     assert np.allclose(G0, G1, atol=1e-13)
+
+
+# ---------------------------------------------------------------- l <= 3
+def _sphere_rule(nt=8, nphi=16):
+    """Product rule on the unit sphere, exact for polynomials of degree <= 15:
+    Gauss-Legendre in cos(theta) times the trapezoid in phi."""
+    x, w = np.polynomial.legendre.leggauss(nt)
+    phi = 2.0 * np.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(x, phi, indexing="ij")
+    st = np.sqrt(1.0 - ct * ct)
+    u = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    wt = (w[:, None] * np.full(nphi, 2.0 * np.pi / nphi)[None, :]).reshape(-1)
+    return u, wt
+
+
+def test_real_harmonics_orthonormal_on_sphere():
+    """int Y_i Y_j dOmega = delta_ij for all 16 functions of l <= 3 (a wrong
+    constant, a wrong polynomial or a repeated function fails this)."""
+    u, wt = _sphere_rule()
+    Y = kb.solid_harmonics(u, 3)                 # r = 1
+    G = (Y * wt[:, None]).T @ Y
+    assert np.max(np.abs(G - np.eye(16))) < 1e-14
+
+
+def test_addition_theorem():
+    """sum_m Y_lm(u)^2 = (2l + 1) / (4 pi) for every direction u and each l."""
+    u = np.random.default_rng(11).normal(size=(50, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    Y = kb.solid_harmonics(u, 3)
+    for l in range(4):
+        s = np.sum(Y[:, l * l:(l + 1) ** 2] ** 2, axis=1)
+        assert np.allclose(s, (2 * l + 1) / (4 * np.pi), rtol=0, atol=1e-15)
+
+
+def test_solid_harmonics_are_harmonic():
+    """r^l Y_lm has zero Laplacian; for polynomials of degree <= 3 the second
+    central difference with unit step equals the second derivative exactly."""
+    rng = np.random.default_rng(12)
+    d = rng.uniform(-2, 2, size=(40, 3))
+    lap = -6.0 * kb.solid_harmonics(d, 3)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1.0
+        lap += kb.solid_harmonics(d + e, 3) + kb.solid_harmonics(d - e, 3)
+    assert np.max(np.abs(lap)) < 1e-12
+    # degree and parity: scaling d by t scales the l block by t^l
+    t = 1.7
+    for l in range(4):
+        sl = slice(l * l, (l + 1) ** 2)
+        assert np.allclose(kb.solid_harmonics(t * d, 3)[:, sl], t ** l * kb.solid_harmonics(d, 3)[:, sl],
+                           rtol=1e-13, atol=1e-13)
+
+
+def test_radial_norm_by_quadrature():
+    from scipy.integrate import quad
+    for l in range(4):
+        for sigma in (0.5, 0.9):
+            N = kb.radial_norm(l, sigma)
+            val, _ = quad(lambda r: N * N * r ** (2 * l + 2) * np.exp(-r * r / sigma ** 2), 0, np.inf,
+                          epsabs=1e-14, epsrel=1e-13)
+            assert val == pytest.approx(1.0, abs=1e-12)
+
+
+def test_lmax3_projectors_orthonormal_on_fine_grid():
+    """The 16 projectors of one atom are orthonormal in the continuum; on a
+    grid with h << sigma the grid Gram matrix is the identity to quadrature
+    precision (off the grid point too), and l <= 1 reproduces the s/p set."""
+    g = grid.build_grid("sphere", 0.14, radius=4.6)
+    pos = np.array([[0.031, -0.047, 0.022]])
+    ps = kb.build_projectors(g, pos, np.ones((1, 16)), rc=4.5, sigma=0.7, lmax=3)
+    G = g.dv * ps.gamma[0].T @ ps.gamma[0]
+    assert np.max(np.abs(G - np.eye(16))) < 1e-10
+    ps1 = kb.build_projectors(g, pos, np.ones((1, 4)), rc=4.5, sigma=0.7, lmax=1)
+    assert np.allclose(ps1.gamma[0], ps.gamma[0][:, :4], rtol=1e-14, atol=1e-16)
+    ns, npn = kb.projector_norms(0.7)
+    d = g.xyz[ps.idx[0]] - pos[0]
+    e = np.exp(-(d * d).sum(1) / (2 * 0.49))
+    assert np.allclose(ps1.gamma[0], np.c_[ns * e, npn * d * e[:, None]], rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("lmax", [0, 2, 3])
+def test_vnl_hermitian_rank_and_scatter_lmax(lmax):
+    """V_nl with (lmax+1)^2 projectors per atom: symmetric, rank <= nproj * nat,
+    and the coloured scatter equals the plain per-atom sum."""
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.25, nat=3, atom_radius=0.6, rc=1.0)
+    g, atoms, _ = hamiltonian.build_system(w, with_projectors=False)
+    npj = (lmax + 1) ** 2
+    D = np.random.default_rng(20 + lmax).uniform(0.5, 2.0, size=(atoms.pos.shape[0], npj))
+    ps = kb.build_projectors(g, atoms.pos, D, w.rc, w.sigma, lmax=lmax)
+    assert ps.gamma[0].shape[1] == npj
+    Vd = kb.apply_nonlocal(ps, np.eye(g.np))
+    assert np.max(np.abs(Vd - Vd.T)) < 1e-13 * np.max(np.abs(Vd))
+    s = np.linalg.svd(Vd, compute_uv=False)
+    assert np.sum(s > 1e-10 * s[0]) <= npj * ps.nat
+    # brute force: V = h^3 sum_A sum_i D_Ai g_Ai g_Ai^T on the full grid
+    want = np.zeros((g.np, g.np))
+    for a in range(ps.nat):
+        for i in range(npj):
+            f = np.zeros(g.np)
+            f[ps.idx[a]] = ps.gamma[a][:, i]
+            want += g.dv * D[a, i] * np.outer(f, f)
+    assert np.max(np.abs(Vd - want)) < 1e-13 * np.max(np.abs(want))
+
+
+def test_complex_states_split_into_real_and_imaginary_parts():
+    """The projectors are real, so V_nl (a + i b) = V_nl a + i V_nl b and the
+    projections of a complex state are P(a) + i P(b)."""
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=1.6, h=0.25, nat=3, atom_radius=0.6, rc=1.0)
+    g, atoms, _ = hamiltonian.build_system(w, with_projectors=False)
+    ps = kb.build_projectors(g, atoms.pos, np.ones((atoms.pos.shape[0], 9)), w.rc, w.sigma, lmax=2)
+    rng = np.random.default_rng(21)
+    a, b = rng.uniform(-1, 1, size=(2, 3, g.np))
+    z = a + 1j * b
+    assert np.allclose(kb.project(ps, z), kb.project(ps, a) + 1j * kb.project(ps, b), rtol=0, atol=1e-15)
+    assert np.allclose(kb.apply_nonlocal(ps, z), kb.apply_nonlocal(ps, a) + 1j * kb.apply_nonlocal(ps, b),
+                       rtol=0, atol=1e-14)
+    # Hermitian on complex states: <x|V y> = conj(<y|V x>)
+    x, y = z[0], z[1]
+    lhs = np.vdot(x, kb.apply_nonlocal(ps, y))
+    rhs = np.conj(np.vdot(y, kb.apply_nonlocal(ps, x)))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)

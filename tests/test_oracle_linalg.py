@@ -54,3 +54,17 @@ def test_rayleigh_ritz_matches_eigh_and_diagonalises():
     P1 = psi.T @ psi
     P2 = p2.T @ p2
     assert np.allclose(P1, P2, atol=1e-10 / g.dv)
+
+
+def test_overlap_of_complex_states_is_hermitian_and_splits():
+    """S = h^3 Psi^H Psi for complex states: Hermitian, positive definite,
+    with real part S(a) + S(b) and imaginary part S(a, b) - S(b, a)."""
+    rng = np.random.default_rng(31)
+    a, b = rng.uniform(-1, 1, size=(2, 6, 50))
+    z = a + 1j * b
+    S = linalg.overlap(z, 0.3)
+    assert np.allclose(S, S.conj().T, rtol=0, atol=1e-14)
+    assert np.min(np.linalg.eigvalsh(S)) > 0
+    assert np.allclose(S.real, 0.3 * (a @ a.T + b @ b.T), rtol=0, atol=1e-13)
+    assert np.allclose(S.imag, 0.3 * (a @ b.T - b @ a.T), rtol=0, atol=1e-13)
+    assert np.allclose(linalg.overlap(a, 0.3, b), 0.3 * a @ b.T, rtol=0, atol=1e-13)
