@@ -44,7 +44,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def setup(w, dtype, B):
+def setup(w, dtype, B, lmax=1):
     import torch
     import paper_1306_2953_amd as rsd
     g = rsd.Grid.for_workload(w)
@@ -53,7 +53,8 @@ def setup(w, dtype, B):
     v = synthetic.potential_for(w, xyz, atoms)
     nl = None
     if atoms is not None:
-        nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=-(-w.nstates // B) * B)
+        nl = rsd.NonLocal(g, atoms.pos, synthetic.couplings_lmax(w, atoms, lmax), w.rc, w.sigma,
+                          max_states=-(-w.nstates // B) * B, lmax=lmax)
     rng = synthetic.rng_after_atoms(w)
     npdt = np.float64 if dtype == "f64" else np.float32
     psi = synthetic.draw_states(rng, w.nstates, g.np).astype(npdt)
@@ -65,7 +66,7 @@ def setup(w, dtype, B):
     nblk = int(tpsi.shape[0])        # the last block padded with zero states when B does not divide N
     proj = None
     if nl is not None:
-        proj = torch.empty((nblk, nl.nat, 4, B), dtype=tpsi.dtype, device=dev)
+        proj = torch.empty((nblk, nl.nat, nl.nproj, B), dtype=tpsi.dtype, device=dev)
     return dict(g=g, nl=nl, v=tv, psi=tpsi, hpsi=thpsi, proj=proj, nblk=nblk, B=B)
 
 
@@ -81,10 +82,10 @@ def time_calls(fn, n, stream):
     return e0.elapsed_time(e1) / n * 1e-3     # seconds per call
 
 
-def run_gpu(w, dtype, B, steps, warmup):
+def run_gpu(w, dtype, B, steps, warmup, lmax=1):
     import torch
     import paper_1306_2953_amd as rsd
-    S = setup(w, dtype, B)
+    S = setup(w, dtype, B, lmax)
     stream = torch.cuda.current_stream()
     g, nl = S["g"], S["nl"]
 
@@ -632,6 +633,11 @@ def main():
                                              "frac", "np", "N", "B", "nblk")}
         extra[w5.name]["note"] = "240 states in 4 blocks of 64 (16 zero padding states, not counted)"
     if primary:
+        # projectors to l = 3 (16 per atom instead of 4): the same H psi call
+        for wk, dt in ((w, dtype), (synthetic.WORKLOADS["sphere_r12_h0.2_fp32"], "f32")):
+            rl = run_gpu(wk, dt, B, a.steps, a.warmup, lmax=3)
+            extra[f"{wk.name}_lmax3"] = {k: rl[k] for k in ("ptstates_per_s", "t_step", "t_proj")}
+            log(f"{wk.name} lmax 3: {extra[f'{wk.name}_lmax3']}")
         extra["hartree"] = hartree_rate(w)
         log(f"hartree: {extra['hartree']}")
     scf = None

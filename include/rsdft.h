@@ -23,7 +23,12 @@
  *    are never stored.
  *  - dtype selects the storage type of fields: RS_F64 (double) or RS_F32
  *    (float).  Small matrices (overlap, subspace Hamiltonian, Cholesky
- *    factor, eigenvectors, eigenvalues) are always double.
+ *    factor, eigenvectors, eigenvalues) are always double.  rs_hpsi_block,
+ *    rs_project_nl, rs_apply_nl and rs_overlap also take complex states
+ *    (eq. (1b) conjugates them): RS_C128 (double re, im) and RS_C64 (float
+ *    re, im), the two parts interleaved, so a block of B complex states is
+ *    laid out as a block of 2B real columns (re of state 0, im of state 0,
+ *    re of state 1, ...); B <= 32.
  *  - Host arrays passed to *_create calls are copied; handles own their
  *    device tables and scratch, sized at creation, so the field calls never
  *    allocate device memory.
@@ -53,6 +58,8 @@ typedef int rs_status;
 
 #define RS_F64 0
 #define RS_F32 1
+#define RS_C128 2   /* complex, double parts */
+#define RS_C64 3    /* complex, float parts  */
 
 /* Contraction precision of the point-summed products (overlap, subspace
  * matrix, rotations).  RS_PREC_NATIVE: the storage type, with FP64
@@ -140,25 +147,37 @@ rs_status rs_grid_export(const rs_grid *g, int32_t *inner, int32_t *boundary,
 
 /* ------------------------------------------------------- non-local part
  * Eq. (6), Sec. 5.3, with a diagonal coupling: V_nl = sum_A sum_i
- * |gamma_A,i> D_A,i <gamma_A,i|, i in {s, p_x, p_y, p_z}, where
- * gamma_s = N_s exp(-r^2 / 2 sigma^2), gamma_p_a = N_p r_a exp(-r^2/2 sigma^2),
- * N_s = (pi^1.5 sigma^3)^-1/2, N_p = (pi^1.5 sigma^5 / 2)^-1/2, nonzero for
- * |r_p - R_A|^2 <= rc^2 (minimum image on periodic grids).  Atoms are split
- * into colour groups with disjoint spheres (greedy, atom order; Fig. "colors").
+ * |gamma_A,i> D_A,i <gamma_A,i|, i running over the (lmax+1)^2 pairs (l, m),
+ * l = 0..lmax <= 3, m = -l..l:
+ *   gamma_lm(r) = N_l r^l Y_lm(r/|r|) exp(-r^2 / 2 sigma^2),
+ * Y_lm the real spherical harmonics (unit-normalised on the sphere) and
+ * N_l = (Gamma(l + 3/2) sigma^(2l+3) / 2)^(-1/2), so that each gamma has
+ * unit continuum norm; nonzero for |r_p - R_A|^2 <= rc^2 (minimum image on
+ * periodic grids).  Projector order within an atom: l ascending; l = 1:
+ * x, y, z; l = 2: xy, yz, 3z^2 - r^2, xz, x^2 - y^2; l = 3: y(3x^2 - y^2),
+ * xyz, y(5z^2 - r^2), z(5z^2 - 3r^2), x(5z^2 - r^2), z(x^2 - y^2),
+ * x(x^2 - 3y^2).  lmax = 1 is the s, p_x, p_y, p_z set
+ * (N_s exp(-r^2/2 sigma^2), N_p r_a exp(-r^2/2 sigma^2)).  Atoms are split
+ * into colour groups with disjoint spheres (greedy, atom order; Fig.
+ * "colors").  The projectors are real, so a complex state's projections
+ * are those of its real and imaginary parts.
  *
- * pos [nat][3] (bohr) and D [nat][4] (Ha) are host arrays.  max_states is the
- * largest nblk*B later passed to the field calls (sizes scratch).  On a
- * host-only grid the set is built on the host only (export works, field
- * calls return RS_EINVAL). */
+ * pos [nat][3] (bohr) and D [nat][(lmax+1)^2] (Ha) are host arrays.
+ * max_states is the largest number of real state columns later passed to
+ * the field calls (nblk*B, or 2*nblk*B for complex states; sizes scratch).
+ * On a host-only grid the set is built on the host only (export works,
+ * field calls return RS_EINVAL).  Errors: RS_EINVAL (null, nat < 0, rc or
+ * sigma <= 0, lmax outside 0..3, max_states outside 1..4096). */
 typedef struct rs_nl rs_nl;
 rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *pos,
-                       const double *D, double rc, double sigma,
+                       const double *D, double rc, double sigma, int32_t lmax,
                        int32_t max_states, rs_nl **out);
 void rs_nl_destroy(rs_nl *nl);
-/* Total sphere entries and number of colour groups (either may be NULL). */
-rs_status rs_nl_info(const rs_nl *nl, int64_t *nnz, int32_t *ncolours);
+/* Total sphere entries, number of colour groups and projectors per atom
+ * ((lmax+1)^2); any pointer may be NULL. */
+rs_status rs_nl_info(const rs_nl *nl, int64_t *nnz, int32_t *ncolours, int32_t *nproj);
 /* Host copies: sph_ptr [nat+1], sph_idx [nnz] (inner-point indices, ascending
- * per atom), gamma [nnz][4], colour [nat].  Any pointer may be NULL. */
+ * per atom), gamma [nnz][nproj], colour [nat].  Any pointer may be NULL. */
 rs_status rs_nl_export(const rs_nl *nl, int64_t *sph_ptr, int64_t *sph_idx,
                        double *gamma, int32_t *colour);
 
@@ -171,21 +190,25 @@ rs_status rs_nl_export(const rs_nl *nl, int64_t *sph_ptr, int64_t *sph_idx,
  *   V_nl: eq. (6) when nl != NULL (projections, then the point-centric sum
  *      over the atoms whose sphere holds the point; no atomics).
  * psi [nblk][np][B] and hpsi [nblk][np][B] must not overlap.  Asynchronous.
- * Errors: RS_EINVAL (B, dtype, pointers, nblk*B > max_states of nl),
- * RS_ENOTSUP (brick other than 4x4x4). */
+ * Complex dtypes: H is real, so each complex state is applied as its real
+ * and imaginary columns (B <= 32).
+ * Errors: RS_EINVAL (B, dtype, pointers, nblk*B real columns > max_states
+ * of nl), RS_ENOTSUP (brick other than 4x4x4). */
 rs_status rs_hpsi_block(const rs_grid *g, const rs_nl *nl, const void *vloc,
                         const void *psi, void *hpsi, int32_t nblk, int32_t B,
                         int32_t dtype, void *stream);
 
 /* First part of eq. (6): proj[blk][A][i][s] = h^3 sum_{p in sphere A}
- * gamma_A,i(p) psi[blk][p][s] (D not applied), FP64 accumulation, stored in
- * dtype.  Asynchronous. */
+ * gamma_A,i(p) psi[blk][p][s] (D not applied), i < nproj, FP64
+ * accumulation, stored in dtype (complex: proj[blk][A][i][s] complex, the
+ * real layout with 2B columns).  Asynchronous. */
 rs_status rs_project_nl(const rs_grid *g, const rs_nl *nl, const void *psi,
                         void *proj, int32_t nblk, int32_t B, int32_t dtype,
                         void *stream);
 
 /* Second part of eq. (6): hpsi[blk][p][s] += sum_{A : p in sphere A}
- * sum_i gamma_A,i(p) D_A,i proj[blk][A][i][s].  Asynchronous. */
+ * sum_i gamma_A,i(p) D_A,i proj[blk][A][i][s], i < nproj (complex states as
+ * in rs_project_nl).  Asynchronous. */
 rs_status rs_apply_nl(const rs_grid *g, const rs_nl *nl, const void *proj,
                       void *hpsi, int32_t nblk, int32_t B, int32_t dtype,
                       void *stream);
@@ -203,7 +226,11 @@ void rs_ctx_destroy(rs_ctx *c);
  * only the upper 16x16 blocks are formed (symmetric rank-k product) and
  * mirrored.  Per-chunk (<= 4096 points) partial sums are added in FP64 in a
  * fixed order (bitwise repeatable).  prec must be RS_PREC_NATIVE for RS_F64
- * and RS_PREC_BF16X3 for RS_F32 (else RS_ENOTSUP).  Asynchronous. */
+ * and RS_PREC_BF16X3 for RS_F32 (else RS_ENOTSUP).  Complex states (RS_C128
+ * with RS_PREC_NATIVE, RS_C64 with RS_PREC_BF16X3): S is DEVICE complex
+ * double [N][N] (re, im interleaved), S[j][k] = h^3 sum_p conj(X[p][j])
+ * Y[p][k], formed from the real products of the 2N real columns; needs
+ * 2N <= max_states.  Asynchronous. */
 rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t nblk,
                      int32_t B, int32_t dtype, int32_t prec, void *stream);
 
@@ -221,7 +248,8 @@ rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t
  * start at zero): calls that overlap in time on one GPU (any streams, any
  * threads) race and give wrong results.  The array's device address is
  * looked up once per device, on the first call made with it current.
- * Errors as rs_overlap.  Asynchronous. */
+ * Real dtypes only (RS_F64, RS_F32; complex dtypes return RS_EINVAL);
+ * errors otherwise as rs_overlap.  Asynchronous. */
 rs_status rs_overlap_noalloc(const rs_grid *g, const void *x, const void *y, double *S,
                              int32_t nblk, int32_t B, int32_t dtype, int32_t prec,
                              void *stream);
@@ -308,7 +336,7 @@ rs_status rs_poisson_solve(rs_poisson *p, const double *rho, double *vh, void *s
 typedef struct rs_solver rs_solver;
 typedef struct {
     int32_t m;           /* iterates built per step (H d applications), 1..3 */
-    double  alpha;       /* filter centre weight (0.6)                       */
+    double  alpha;       /* filter centre weight (0.52)                      */
     double  tol;         /* residual threshold of the block stopping rule    */
     int32_t block_stop;  /* nonzero: freeze blocks whose states are all < tol */
     int32_t record;      /* nonzero: keep R0 and sigma of each step for
@@ -325,7 +353,7 @@ typedef struct {
  * nblk * B).  When B does not divide nstates the last block is padded with
  * zero states: they stay zero, get identity pivots in the orthonormalisation
  * and are left out of the Rayleigh-Ritz problem, the stopping rule and the
- * outputs.  opts NULL: m = 3, alpha = 0.6,
+ * outputs.  opts NULL: m = 3, alpha = 0.52,
  * tol = 1e-6, block_stop = 1, record = 0, rr_sweeps = 0.  Allocates all workspaces (about 2(m+1)+3
  * field arrays of np * nstates elements). */
 rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, const void *vloc,

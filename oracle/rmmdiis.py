@@ -26,13 +26,16 @@ reading taken here is:
   4. Orthonormalise all states (Cholesky, eq. 8).
 A state whose lambda is exactly zero keeps psi0.  The filter is
 K r_p = alpha r_p + (1 - alpha)/6 sum of the six nearest neighbours (zero
-outside the domain), alpha = 0.6.  Its symbol alpha + (1 - alpha)/3 sum_a
+outside the domain), alpha = 0.52.  Its symbol alpha + (1 - alpha)/3 sum_a
 cos(k_a h) is 1 at k = 0 and 2 alpha - 1 at the Nyquist corner; with
 alpha = 1/2 it vanishes there, and on a periodic grid with an even number of
 points per edge the alternating vector (-1)^(i+j+k) is then an exact null
 vector of K: no update can change the states' components along it, and the
 random start's share of it stays in the residuals as a floor (~1e-2 on a
-periodic 48^3 box).  alpha = 0.6 keeps the symbol >= 0.2.
+periodic 48^3 box).  Any alpha > 1/2 keeps the symbol positive; 0.52
+(corner symbol 0.04) keeps the filter close to the smoothing it is meant to
+be: the closer alpha is to 1, the more the filter acts like the identity and
+the slower the high-energy residual decays.
 
 With a learned preconditioner K_n (the project's addition, ``oracle.cnn``)
 the network does not replace the filter K_f: it adds a second direction.
@@ -61,14 +64,14 @@ from .linalg import dots, orthonormalize, rayleigh_ritz
 @dataclasses.dataclass
 class Options:
     m: int = 3               # iterates built per step (H d applications)
-    alpha: float = 0.6       # filter centre weight
+    alpha: float = 0.52      # filter centre weight
     tol: float = 1e-6        # residual-norm threshold
     block: int = 32          # block size for the stopping rule
     block_stop: bool = True
 
 
 def filter_precond(g: Grid, r: np.ndarray, nbr: Optional[np.ndarray] = None,
-                   alpha: float = 0.6) -> np.ndarray:
+                   alpha: float = 0.52) -> np.ndarray:
     """K r = alpha r + (1 - alpha)/6 (sum of the 6 nearest neighbours)."""
     if nbr is None:
         nbr = neighbour_table(g)

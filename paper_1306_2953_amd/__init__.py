@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _abi
-from ._abi import (RS_F32, RS_F64, RS_GRID_BOX, RS_GRID_HOST_ONLY, RS_GRID_PERIODIC,
+from ._abi import (RS_C64, RS_C128, RS_F32, RS_F64, RS_GRID_BOX, RS_GRID_HOST_ONLY, RS_GRID_PERIODIC,
                    RS_GRID_SPHERE, RS_GRID_UNION, RS_PREC_BF16X3, RS_PREC_NATIVE, RsError, check, lib)
 
 _KINDS = {"box": RS_GRID_BOX, "periodic": RS_GRID_PERIODIC, "sphere": RS_GRID_SPHERE, "union": RS_GRID_UNION}
@@ -103,17 +103,27 @@ class NonLocal:
     """Kleinman-Bylander projector set (rs_nl)."""
 
     def __init__(self, grid: Grid, pos: np.ndarray, D: np.ndarray, rc: float,
-                 sigma: float, max_states: int):
+                 sigma: float, max_states: int, lmax: int = 1):
+        """D [nat, (lmax+1)^2]; max_states counts real columns (a complex
+        state takes two)."""
+        if not 0 <= int(lmax) <= 3:
+            raise ValueError(f"lmax must be 0..3, got {lmax}")
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
-        D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1, 4)
+        npj = (int(lmax) + 1) ** 2
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        if D.size != pos.shape[0] * npj:
+            raise ValueError(f"D must hold {npj} values per atom for lmax {lmax}, got shape {D.shape}")
+        D = D.reshape(-1, npj)
         self.grid = grid
         self.nat = pos.shape[0]
+        self.lmax = int(lmax)
+        self.max_states = int(max_states)
         self._h = ctypes.c_void_p()
         check(lib().rs_nl_create(grid.handle, self.nat, _ptr(pos), _ptr(D), float(rc),
-                                 float(sigma), int(max_states), ctypes.byref(self._h)))
-        nnz, ncol = ctypes.c_int64(), ctypes.c_int32()
-        check(lib().rs_nl_info(self._h, ctypes.byref(nnz), ctypes.byref(ncol)))
-        self.nnz, self.ncolours = nnz.value, ncol.value
+                                 float(sigma), self.lmax, int(max_states), ctypes.byref(self._h)))
+        nnz, ncol, npr = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().rs_nl_info(self._h, ctypes.byref(nnz), ctypes.byref(ncol), ctypes.byref(npr)))
+        self.nnz, self.ncolours, self.nproj = nnz.value, ncol.value, npr.value
 
     @property
     def handle(self):
@@ -122,7 +132,7 @@ class NonLocal:
     def export(self):
         ptr = np.empty(self.nat + 1, dtype=np.int64)
         idx = np.empty(max(self.nnz, 1), dtype=np.int64)
-        gam = np.empty((max(self.nnz, 1), 4), dtype=np.float64)
+        gam = np.empty((max(self.nnz, 1), self.nproj), dtype=np.float64)
         col = np.empty(max(self.nat, 1), dtype=np.int32)
         check(lib().rs_nl_export(self._h, _ptr(ptr), _ptr(idx), _ptr(gam), _ptr(col)))
         return dict(sph_ptr=ptr, sph_idx=idx[: self.nnz], gamma=gam[: self.nnz],
@@ -148,7 +158,22 @@ def _dtype_code(t) -> int:
         return RS_F64
     if t.dtype == torch.float32:
         return RS_F32
+    if t.dtype == torch.complex128:
+        return RS_C128
+    if t.dtype == torch.complex64:
+        return RS_C64
     raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _real_dtype(t):
+    """float64 for float64/complex128 fields, float32 for float32/complex64."""
+    torch = _torch()
+    return torch.float64 if t.dtype in (torch.float64, torch.complex128) else torch.float32
+
+
+def _columns(psi) -> int:
+    """Real columns per state: 2 for complex states."""
+    return 2 if psi.is_complex() else 1
 
 
 def _stream(stream=None):
@@ -187,25 +212,31 @@ def _check(t, name: str, shape=None, dtype=None, like=None, numel=None):
     return t
 
 
-def _blocks(psi, grid: Grid):
+def _blocks(psi, grid: Grid, complex_ok: bool = False):
     torch = _torch()
     if not isinstance(psi, torch.Tensor):
         raise TypeError("fields must be torch tensors")
     if psi.dim() != 3 or psi.shape[1] != grid.np:
         raise ValueError(f"psi must be [nblk, np={grid.np}, B], got {tuple(psi.shape)}")
-    if psi.dtype not in (torch.float32, torch.float64):
-        raise ValueError(f"fields must be float32 or float64, got {psi.dtype}")
+    ok = (torch.float32, torch.float64) + ((torch.complex64, torch.complex128) if complex_ok else ())
+    if psi.dtype not in ok:
+        extra = " (or complex64, complex128)" if complex_ok else ""
+        raise ValueError(f"fields must be float32 or float64{extra}, got {psi.dtype}")
     B = psi.shape[2]
-    if B < 1 or B > 64 or (B & (B - 1)):
-        raise ValueError(f"B must be a power of two in [1, 64], got {B}")
+    bmax = 32 if psi.is_complex() else 64
+    if B < 1 or B > bmax or (B & (B - 1)):
+        raise ValueError(f"B must be a power of two in [1, {bmax}], got {B}")
     return psi.shape[0], B
 
 
 def hpsi_block(grid: Grid, nl: Optional[NonLocal], vloc, psi, hpsi, stream=None):
-    """hpsi = (T + V + V_nl) psi for psi [nblk, np, B] (rs_hpsi_block)."""
-    nblk, B = _blocks(psi, grid)
+    """hpsi = (T + V + V_nl) psi for psi [nblk, np, B] (rs_hpsi_block); psi
+    real or complex, vloc real of the same precision."""
+    nblk, B = _blocks(psi, grid, complex_ok=True)
     _check(hpsi, "hpsi", like=psi)
-    _check(vloc, "vloc", dtype=psi.dtype, numel=grid.np)
+    _check(vloc, "vloc", dtype=_real_dtype(psi), numel=grid.np)
+    if nl is not None and nblk * B * _columns(psi) > nl.max_states:
+        raise ValueError(f"{nblk * B * _columns(psi)} real columns exceed the projector set's max_states")
     if vloc.device != psi.device:
         raise ValueError("vloc must be on psi's device")
     if hpsi.data_ptr() == psi.data_ptr():
@@ -217,9 +248,11 @@ def hpsi_block(grid: Grid, nl: Optional[NonLocal], vloc, psi, hpsi, stream=None)
 
 
 def project_nl(grid: Grid, nl: NonLocal, psi, proj, stream=None):
-    """proj [nblk, nat, 4, B] = h^3 <gamma_A,i|psi> (rs_project_nl)."""
-    nblk, B = _blocks(psi, grid)
-    _check(proj, "proj", shape=(nblk, nl.nat, 4, B), dtype=psi.dtype)
+    """proj [nblk, nat, nproj, B] = h^3 <gamma_A,i|psi> (rs_project_nl)."""
+    nblk, B = _blocks(psi, grid, complex_ok=True)
+    _check(proj, "proj", shape=(nblk, nl.nat, nl.nproj, B), dtype=psi.dtype)
+    if nblk * B * _columns(psi) > nl.max_states:
+        raise ValueError(f"{nblk * B * _columns(psi)} real columns exceed the projector set's max_states")
     check(lib().rs_project_nl(grid.handle, nl.handle, _dev(psi, "psi"), _dev(proj, "proj"),
                               nblk, B, _dtype_code(psi), _stream(stream)))
     return proj
@@ -227,8 +260,12 @@ def project_nl(grid: Grid, nl: NonLocal, psi, proj, stream=None):
 
 def apply_nl(grid: Grid, nl: NonLocal, proj, hpsi, stream=None):
     """hpsi += sum gamma D proj (rs_apply_nl)."""
-    nblk, B = _blocks(hpsi, grid)
-    _check(proj, "proj", shape=(nblk, nl.nat, 4, B), dtype=hpsi.dtype)
+    nblk, B = _blocks(hpsi, grid, complex_ok=True)
+    _check(proj, "proj", shape=(nblk, nl.nat, nl.nproj, B), dtype=hpsi.dtype)
+    if proj.device != hpsi.device:
+        raise ValueError("proj must be on hpsi's device")
+    if nblk * B * _columns(hpsi) > nl.max_states:
+        raise ValueError(f"{nblk * B * _columns(hpsi)} real columns exceed the projector set's max_states")
     check(lib().rs_apply_nl(grid.handle, nl.handle, _dev(proj, "proj"), _dev(hpsi, "hpsi"),
                             nblk, B, _dtype_code(hpsi), _stream(stream)))
     return hpsi
@@ -305,10 +342,11 @@ class Context:
             L.rs_ctx_destroy(h)
             self._h = None
 
-    def _fields(self, psi):
-        nblk, B = _blocks(psi, self.grid)
-        if nblk * B > self.max_states:
-            raise ValueError(f"{nblk * B} states exceed the context's max_states {self.max_states}")
+    def _fields(self, psi, complex_ok: bool = False):
+        nblk, B = _blocks(psi, self.grid, complex_ok)
+        if nblk * B * _columns(psi) > self.max_states:
+            raise ValueError(f"{nblk * B * _columns(psi)} real columns exceed the context's max_states "
+                             f"{self.max_states}")
         return nblk, B
 
     def _square(self, A, name):
@@ -325,17 +363,21 @@ class Context:
     def _prec(t, prec):
         if prec is not None:
             return prec
-        return RS_PREC_NATIVE if _dtype_code(t) == RS_F64 else RS_PREC_BF16X3
+        return RS_PREC_NATIVE if _dtype_code(t) in (RS_F64, RS_C128) else RS_PREC_BF16X3
 
     def overlap(self, x, y, S=None, prec=None, stream=None):
-        """S [N, N] (float64) = h^3 X^T Y (rs_overlap)."""
-        nblk, B = self._fields(x)
+        """S [N, N] = h^3 X^H Y (rs_overlap): float64, or complex128 for
+        complex states."""
+        nblk, B = self._fields(x, complex_ok=True)
         _check(y, "y", like=x)
         torch = _torch()
         N = nblk * B
+        sdt = torch.complex128 if x.is_complex() else torch.float64
         if S is None:
-            S = torch.empty((N, N), dtype=torch.float64, device=x.device)
-        _check(S, "S", shape=(N, N), dtype=torch.float64)
+            S = torch.empty((N, N), dtype=sdt, device=x.device)
+        _check(S, "S", shape=(N, N), dtype=sdt)
+        if S.device != x.device:
+            raise ValueError("S must be on x's device")
         check(lib().rs_overlap(self._h, _dev(x, "x"), _dev(y, "y"), _dev(S, "S"), nblk, B,
                                _dtype_code(x), self._prec(x, prec), _stream(stream)))
         return S
@@ -401,7 +443,7 @@ class Scf:
 
     def __init__(self, grid: Grid, nl: Optional[NonLocal], vion, nstates: int, B: int, nocc: int,
                  dtype=None, eig_steps: int = 3, mix: float = 0.3, history: int = 5,
-                 m: int = 3, alpha: float = 0.6, tol: float = 1e-6, block_stop: bool = True):
+                 m: int = 3, alpha: float = 0.52, tol: float = 1e-6, block_stop: bool = True):
         torch = _torch()
         _check(vion, "vion", dtype=torch.float64, numel=grid.np)
         if not vion.is_cuda:
@@ -455,7 +497,7 @@ class Eigensolver:
     """RMM-DIIS eigensolver over the states of one grid (rs_solver)."""
 
     def __init__(self, grid: Grid, nl: Optional[NonLocal], vloc, nstates: int, B: int,
-                 m: int = 3, alpha: float = 0.6, tol: float = 1e-6, block_stop: bool = True,
+                 m: int = 3, alpha: float = 0.52, tol: float = 1e-6, block_stop: bool = True,
                  record: bool = False, rr_sweeps: int = 0):
         _check(vloc, "vloc", numel=grid.np)
         if vloc.dim() != 1:

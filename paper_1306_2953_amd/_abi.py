@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsdft.so
 RS_OK, RS_EINVAL, RS_ENOTPOSDEF, RS_ENONFINITE, RS_EHIP, RS_ENOMEM, RS_ENOTSUP, RS_ENOTCONV = range(8)
 RS_CNN_NPARAM = 2162
 RS_F64, RS_F32 = 0, 1
+RS_C128, RS_C64 = 2, 3          # complex states, (re, im) interleaved
 RS_PREC_NATIVE, RS_PREC_BF16X3 = 0, 1
 RS_GRID_BOX, RS_GRID_PERIODIC, RS_GRID_SPHERE, RS_GRID_UNION = 0, 1, 2, 3
 RS_GRID_HOST_ONLY = 1
@@ -53,9 +54,9 @@ SIGNATURES = {
     "rs_grid_destroy": (None, [P]),
     "rs_grid_info": (ctypes.c_int, [P, PI64, PI64, PI64, PI32, PI32]),
     "rs_grid_export": (ctypes.c_int, [P, P, P, P, P]),
-    "rs_nl_create": (ctypes.c_int, [P, I32, P, P, F64, F64, I32, ctypes.POINTER(P)]),
+    "rs_nl_create": (ctypes.c_int, [P, I32, P, P, F64, F64, I32, I32, ctypes.POINTER(P)]),
     "rs_nl_destroy": (None, [P]),
-    "rs_nl_info": (ctypes.c_int, [P, PI64, PI32]),
+    "rs_nl_info": (ctypes.c_int, [P, PI64, PI32, PI32]),
     "rs_nl_export": (ctypes.c_int, [P, P, P, P, P]),
     "rs_hpsi_block": (ctypes.c_int, [P, P, P, P, P, I32, I32, I32, P]),
     "rs_project_nl": (ctypes.c_int, [P, P, P, P, I32, I32, I32, P]),

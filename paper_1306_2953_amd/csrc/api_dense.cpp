@@ -61,11 +61,22 @@ const int *ctx_sweeps(const rs_ctx *c) { return c->w.sweeps.as<int>(); }
 
 extern "C" rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t nblk, int32_t B,
                                 int32_t dtype, int32_t prec, void *stream) {
+    // complex states: the real product of the 2N interleaved columns, then
+    // the fold into the Hermitian N x N matrix
+    const bool cplx = dtype == RS_C128 || dtype == RS_C64;
+    if (cplx) {
+        if (B > 32) return rs::fail(RS_EINVAL, "rs_overlap: complex blocks hold at most 32 states");
+        dtype = dtype == RS_C128 ? RS_F64 : RS_F32;
+        B *= 2;
+    }
     rs_status st = check(c, nblk, B, dtype, prec, "rs_overlap");
     if (st) return st;
     if (!x || !y || !S) return rs::fail(RS_EINVAL, "rs_overlap: null pointer");
     const double dv = c->g->h * c->g->h * c->g->h;
-    return rs::gram(c->w, x, y, c->g->np, B, nblk, dtype, prec, dv, S, 0, (hipStream_t)stream);
+    const hipStream_t s = (hipStream_t)stream;
+    if (!cplx) return rs::gram(c->w, x, y, c->g->np, B, nblk, dtype, prec, dv, S, 0, s);
+    if ((st = rs::gram(c->w, x, y, c->g->np, B, nblk, dtype, prec, dv, c->A.as<double>(), 0, s))) return st;
+    return rs::complex_fold(c->A.as<double>(), S, nblk * B / 2, s);
 }
 
 extern "C" rs_status rs_rotate(rs_ctx *c, void *psi, const double *X, int32_t nblk, int32_t B, int32_t dtype,

@@ -1062,6 +1062,18 @@ jacobi_sort_kernel(const double *__restrict__ diag, const double *__restrict__ V
 
 // Padded states (index >= n of an N x N matrix): identity on their
 // diagonal, so Cholesky and the eigensolver leave them untouched.
+// S[j][k] = <x_j|y_k> for complex states from the real products of their
+// parts: (re re + im im) + i (re im' - im re').
+__global__ void complex_fold_kernel(const double *__restrict__ G, double *__restrict__ S, int N) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const int j = (int)(e / N), k = (int)(e % N);
+    const int64_t M = 2 * (int64_t)N;
+    const double *r0 = G + (2 * j) * M, *r1 = G + (2 * j + 1) * M;
+    S[2 * e] = r0[2 * k] + r1[2 * k + 1];
+    S[2 * e + 1] = r0[2 * k + 1] - r1[2 * k];
+}
+
 __global__ void pad_identity_kernel(double *__restrict__ S, int N, int n) {
     const int i = n + blockIdx.x * 256 + threadIdx.x;
     if (i < N) S[(int64_t)i * N + i] = 1.0;
@@ -1338,6 +1350,13 @@ rs_status dense_work_init(DenseWork &w, int64_t np, int max_states) {
 }  // namespace rs
 
 namespace rs {
+
+rs_status complex_fold(const double *G, double *S, int N, hipStream_t st) {
+    const int64_t n2 = (int64_t)N * N;
+    hipLaunchKernelGGL(complex_fold_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, G, S, N);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
 
 rs_status pad_identity(double *S, int N, int n, hipStream_t st) {
     if (n >= N) return RS_OK;

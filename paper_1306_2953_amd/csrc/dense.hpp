@@ -53,6 +53,11 @@ rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStrea
 // 30) bounds the work (30 reaches full FP64 accuracy from any start).
 rs_status eigh(DenseWork &w, double *A, double *V, double *evals, int N, hipStream_t st,
                int max_sweeps = 30);
+// Complex overlap from the real one of interleaved columns: G is the
+// 2N x 2N real product (column 2j = re of state j, 2j + 1 = im), S the
+// N x N complex matrix (re, im interleaved) with
+// S[j][k] = (G[2j][2k] + G[2j+1][2k+1]) + i (G[2j][2k+1] - G[2j+1][2k]).
+rs_status complex_fold(const double *G, double *S, int N, hipStream_t st);
 // Padded states n..N-1 (all zero): S[i][i] = 1 for i >= n.
 rs_status pad_identity(double *S, int N, int n, hipStream_t st);
 // Eigenpairs of the leading n x n block of A (N x N); V = diag(V_n, I),

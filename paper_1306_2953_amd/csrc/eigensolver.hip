@@ -477,7 +477,7 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     s->prec = dtype == RS_F64 ? RS_PREC_NATIVE : RS_PREC_BF16X3;
     rs_solver_opts o;
     o.m = 3;
-    o.alpha = 0.6;
+    o.alpha = 0.52;
     o.tol = 1e-6;
     o.block_stop = 1;
     o.record = 0;

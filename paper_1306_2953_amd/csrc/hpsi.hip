@@ -180,7 +180,7 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
           uint32_t lane_off, const uint32_t *tbl, const T *__restrict__ vloc, T vconst, T pre, T w0,
           T w1, T w2, T w3, const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
           const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
-          const T *__restrict__ dpl, int dps) {
+          const T *__restrict__ dpl, int npj, int B) {
     constexpr int NP = 16 * NZ;
     Slots<T, ROW, FAST> nb[6], me;
 #pragma unroll
@@ -263,19 +263,25 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
         acc[k] = pre * acc[k] + vp * own[k];
     }
     // non-local part 2, point-centric: sum over the atoms whose sphere holds
-    // the point of gamma_A,i(p) * (D_A,i P_A,i,s)
+    // the point of gamma_A,i(p) * (D_A,i P_A,i,s), i < npj
     if (brick_nl != nullptr && brick_nl[b]) {
-        const int q4 = dps / 4;
+        const int dps = npj * B;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-                const int q = Z0 * 16 + k;
+            const int q = Z0 * 16 + k;
             if (me.has(q)) {
                 const int p = me.point(q);
                 const int e1 = pt_ptr[p + 1];
                 for (int e = pt_ptr[p]; e < e1; ++e) {
-                    const T *g = ent_gamma + 4 * (int64_t)e;
+                    const T *g = ent_gamma + npj * (int64_t)e;
                     const T *d = dpl + ent_atom[e] * dps;
-                    acc[k] += g[0] * d[0] + g[1] * d[q4] + g[2] * d[2 * q4] + g[3] * d[3 * q4];
+                    if (npj == 4) {
+                        acc[k] += g[0] * d[0] + g[1] * d[B] + g[2] * d[2 * B] + g[3] * d[3 * B];
+                    } else {
+                        T t = g[0] * d[0];
+                        for (int i = 1; i < npj; ++i) t += g[i] * d[i * B];
+                        acc[k] += t;
+                    }
                 }
             }
         }
@@ -299,7 +305,7 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
                   T pre, T w0, T w1, T w2, T w3,
                   const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
                   const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
-                  const T *__restrict__ dp, int nat) {
+                  const T *__restrict__ dp, int nat, int npj) {
     constexpr int PARTS = 4 / NZ;
     constexpr int ROW = B * (int)sizeof(T);
     __shared__ uint32_t tbl_all[FAST ? 1 : 4 * 7 * 64];
@@ -342,12 +348,11 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
     const rsrc_t rp = make_rsrc(psi + blk0 * blk_elems, bytes);
     const rsrc_t rh = make_rsrc(hpsi + blk0 * blk_elems, bytes);
     const uint32_t lane_off = (uint32_t)(((blk - blk0) * blk_elems + s) * sizeof(T));
-    const T *dpl = dp ? dp + (int64_t)blk * nat * 4 * B + s : nullptr;
-    const int dps = 4 * B;
+    const T *dpl = dp ? dp + (int64_t)blk * nat * npj * B + s : nullptr;
     const BrickRec br = bricks[b];
 #define RS_PART(ZZ)                                                                            \
     hpsi_wave<T, ROW, NZ, ZZ, FAST, R>(br, bricks, b, rp, rh, lane_off, tbl, vloc, vconst, pre, w0, w1, w2, w3, \
-                                    brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, dps)
+                                    brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, npj, B)
     if (part == 0) RS_PART(0);
     if constexpr (PARTS >= 2) { if (part == 1) RS_PART(NZ); }
     if constexpr (PARTS == 4) { if (part == 2) RS_PART(2 * NZ); if (part == 3) RS_PART(3 * NZ); }
@@ -567,11 +572,11 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
 }
 
 // Projector term added to an H psi computed without it: hpsi += sum over the
-// spheres holding the point of gamma_A,i(p) (D_A,i P_A,i), one lane per
-// (state, point) of the points that lie in a sphere (eq. 6).  A lane serves
-// up to 4 blocks: the entry loads are shared and the 4 updates are
+// spheres holding the point of gamma_A,i(p) (D_A,i P_A,i), i < NPJ, one lane
+// per (state, point) of the points that lie in a sphere (eq. 6).  A lane
+// serves up to 4 blocks: the entry loads are shared and the 4 updates are
 // independent.
-template <typename T>
+template <typename T, int NPJ>
 __global__ void __launch_bounds__(256)
 nl_add_kernel(const int32_t *__restrict__ nl_pts, int64_t nnl, const int32_t *__restrict__ pt_ptr,
               const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma, const T *__restrict__ dp,
@@ -582,18 +587,22 @@ nl_add_kernel(const int32_t *__restrict__ nl_pts, int64_t nnl, const int32_t *__
     const int nb = min(4, nblk - blk0);
     const int p = nl_pts[idx / B];
     const int s = (int)(idx % B);
-    const int64_t dstride = (int64_t)nat * 4 * B;
+    const int64_t dstride = (int64_t)nat * NPJ * B;
     const T *dpl = dp + blk0 * dstride + s;
     T acc[4] = {T(0), T(0), T(0), T(0)};
     for (int e = pt_ptr[p], e1 = pt_ptr[p + 1]; e < e1; ++e) {
-        const T *g = ent_gamma + 4 * (int64_t)e;
-        const T g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
-        const T *d = dpl + ent_atom[e] * 4 * B;
+        T g[NPJ];
+#pragma unroll
+        for (int i = 0; i < NPJ; ++i) g[i] = ent_gamma[NPJ * (int64_t)e + i];
+        const T *d = dpl + ent_atom[e] * NPJ * B;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (k < nb) {
                 const T *dk = d + k * dstride;
-                acc[k] += g0 * dk[0] + g1 * dk[B] + g2 * dk[2 * B] + g3 * dk[3 * B];
+                T t = g[0] * dk[0];
+#pragma unroll
+                for (int i = 1; i < NPJ; ++i) t += g[i] * dk[i * B];
+                acc[k] += t;
             }
     }
 #pragma unroll
@@ -607,45 +616,43 @@ nl_add_kernel(const int32_t *__restrict__ nl_pts, int64_t nnl, const int32_t *__
 // Non-local part 1 (eq. 6 integrals), stage 1: one work-group per (chunk of
 // <= 512 sphere entries of one atom, block).  Lanes: state s, row r; rows
 // stride through the chunk; FP64 sums are reduced over rows in a fixed tree.
-template <typename T, int B>
+template <typename T, int B, int NPJ>
 __global__ void __launch_bounds__(256)
 nl_partial_kernel(const int32_t *__restrict__ chunk_beg, const int32_t *__restrict__ chunk_end,
                   const int32_t *__restrict__ sph_idx, const T *__restrict__ gamma,
                   const T *__restrict__ psi, int64_t blk_stride, double *__restrict__ partial,
                   int nchunks) {
     constexpr int R = 256 / B;
-    __shared__ double red[4][256];
+    __shared__ double red[NPJ][256];
     const int chunk = blockIdx.x, blk = blockIdx.y;
     const int s = threadIdx.x % B, r = threadIdx.x / B;
     const int e0 = chunk_beg[chunk], e1 = chunk_end[chunk];
     psi += blk * blk_stride;
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    double a[NPJ];
+#pragma unroll
+    for (int i = 0; i < NPJ; ++i) a[i] = 0.0;
     // unrolled so that several entries' gathers are in flight per thread
 #pragma unroll 4
     for (int e = e0 + r; e < e1; e += R) {
         const double x = (double)psi[sph_idx[e] * B + s];
-        const T *g = gamma + 4 * (int64_t)e;
-        a0 += (double)g[0] * x;
-        a1 += (double)g[1] * x;
-        a2 += (double)g[2] * x;
-        a3 += (double)g[3] * x;
+        const T *g = gamma + NPJ * (int64_t)e;
+#pragma unroll
+        for (int i = 0; i < NPJ; ++i) a[i] += (double)g[i] * x;
     }
-    red[0][threadIdx.x] = a0;
-    red[1][threadIdx.x] = a1;
-    red[2][threadIdx.x] = a2;
-    red[3][threadIdx.x] = a3;
+#pragma unroll
+    for (int i = 0; i < NPJ; ++i) red[i][threadIdx.x] = a[i];
     __syncthreads();
 #pragma unroll
     for (int st = R / 2; st > 0; st >>= 1) {
         if (r < st)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + st * B];
+            for (int i = 0; i < NPJ; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + st * B];
         __syncthreads();
     }
     if (r == 0)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            partial[(((int64_t)blk * nchunks + chunk) * 4 + i) * B + s] = red[i][s];
+        for (int i = 0; i < NPJ; ++i)
+            partial[(((int64_t)blk * nchunks + chunk) * NPJ + i) * B + s] = red[i][s];
 }
 
 // Stage 2: sum an atom's chunks in order; P = h^3 sum, DP = D * P.
@@ -653,19 +660,19 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 nl_final_kernel(const int32_t *__restrict__ atom_chunk0, const double *__restrict__ partial,
                 const double *__restrict__ D, T *__restrict__ proj, T *__restrict__ dp,
-                int nat, int nchunks, int B, int64_t total, double dv) {
+                int nat, int npj, int nchunks, int B, int64_t total, double dv) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     const int s = (int)(idx % B);
-    const int i = (int)((idx / B) % 4);
-    const int A = (int)((idx / (4 * B)) % nat);
-    const int64_t blk = idx / (4 * (int64_t)B * nat);
+    const int i = (int)((idx / B) % npj);
+    const int A = (int)((idx / (npj * B)) % nat);
+    const int64_t blk = idx / (npj * (int64_t)B * nat);
     double sum = 0.0;
     for (int c = atom_chunk0[A]; c < atom_chunk0[A + 1]; ++c)
-        sum += partial[((blk * nchunks + c) * 4 + i) * B + s];
+        sum += partial[((blk * nchunks + c) * npj + i) * B + s];
     const double P = dv * sum;
     if (proj) proj[idx] = (T)P;
-    dp[idx] = (T)(D[A * 4 + i] * P);
+    dp[idx] = (T)(D[A * npj + i] * P);
 }
 
 // Standalone non-local part 2 (rs_apply_nl): hpsi += sum gamma D proj, one
@@ -674,7 +681,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 nl_apply_kernel(const int32_t *__restrict__ pt_ptr, const int32_t *__restrict__ ent_atom,
                 const T *__restrict__ ent_gamma, const double *__restrict__ D,
-                const T *__restrict__ proj, T *__restrict__ hpsi, int64_t np, int B, int nat) {
+                const T *__restrict__ proj, T *__restrict__ hpsi, int64_t np, int B, int nat, int npj) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int blk = blockIdx.y;
     if (idx >= np * B) return;
@@ -682,14 +689,13 @@ nl_apply_kernel(const int32_t *__restrict__ pt_ptr, const int32_t *__restrict__ 
     const int s = (int)(idx % B);
     const int k0 = pt_ptr[p], k1 = pt_ptr[p + 1];
     if (k0 == k1) return;
-    const T *pb = proj + (int64_t)blk * nat * 4 * B;
+    const T *pb = proj + (int64_t)blk * nat * npj * B;
     T acc = T(0);
     for (int k = k0; k < k1; ++k) {
         const int A = ent_atom[k];
-        const T *g = ent_gamma + 4 * (int64_t)k;
-        const T *pa = pb + A * 4 * B + s;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc += g[i] * (T)D[A * 4 + i] * pa[i * B];
+        const T *g = ent_gamma + npj * (int64_t)k;
+        const T *pa = pb + A * npj * B + s;
+        for (int i = 0; i < npj; ++i) acc += g[i] * (T)D[A * npj + i] * pa[i * B];
     }
     T *y = hpsi + (int64_t)blk * np * B + idx;
     *y = *y + acc;
@@ -708,22 +714,32 @@ rs_status launch_project(const rs_grid *g, const rs_nl *nl, const T *psi, T *pro
     const T *gam = sizeof(T) == 8 ? (const T *)nl->d_gamma64.p : (const T *)nl->d_gamma32.p;
     const int64_t stride = g->np * B;
     dim3 grid1(nl->nchunks, nblk);
+    auto partial = [&](auto npj_c) {
+        constexpr int NPJ = decltype(npj_c)::value;
 #define RS_PARTIAL(BB)                                                                      \
     case BB:                                                                                \
-        hipLaunchKernelGGL((nl_partial_kernel<T, BB>), grid1, dim3(256), 0, st,            \
+        hipLaunchKernelGGL((nl_partial_kernel<T, BB, NPJ>), grid1, dim3(256), 0, st,       \
                            nl->chunk_beg.as<int32_t>(), nl->chunk_end.as<int32_t>(),       \
                            nl->d_sph_idx.as<int32_t>(), gam, psi, stride,                  \
                            nl->partial.as<double>(), nl->nchunks);                         \
         break;
-    switch (B) {
-        RS_PARTIAL(1) RS_PARTIAL(2) RS_PARTIAL(4) RS_PARTIAL(8) RS_PARTIAL(16) RS_PARTIAL(32) RS_PARTIAL(64)
-    }
+        switch (B) {
+            RS_PARTIAL(1) RS_PARTIAL(2) RS_PARTIAL(4) RS_PARTIAL(8) RS_PARTIAL(16) RS_PARTIAL(32) RS_PARTIAL(64)
+        }
 #undef RS_PARTIAL
+    };
+    switch (nl->npj) {
+        case 1: partial(std::integral_constant<int, 1>{}); break;
+        case 4: partial(std::integral_constant<int, 4>{}); break;
+        case 9: partial(std::integral_constant<int, 9>{}); break;
+        case 16: partial(std::integral_constant<int, 16>{}); break;
+        default: return fail(RS_EINVAL, "project: unsupported projector count");
+    }
     RS_HIP(hipGetLastError());
-    const int64_t total = (int64_t)nblk * nl->nat * 4 * B;
+    const int64_t total = (int64_t)nblk * nl->nat * nl->npj * B;
     hipLaunchKernelGGL((nl_final_kernel<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        nl->atom_chunk0.as<int32_t>(), nl->partial.as<double>(), nl->d_D.as<double>(),
-                       proj, (T *)nl->dp.p, nl->nat, nl->nchunks, B, total, nl->dv);
+                       proj, (T *)nl->dp.p, nl->nat, nl->npj, nl->nchunks, B, total, nl->dv);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -751,6 +767,7 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
     const T *egm = with_nl ? (sizeof(T) == 8 ? (const T *)nl->ent_gamma64.p : (const T *)nl->ent_gamma32.p) : nullptr;
     const T *dp = with_nl ? (const T *)nl->dp.p : nullptr;
     const int nat = with_nl ? nl->nat : 0;
+    const int npj = with_nl ? nl->npj : 0;
     const T w0 = (T)w[0], w1 = (T)w[1], w2 = (T)w[2], w3 = (T)w[3];
     // z-marching kernel (FP64): the full stencil when the block splits into
     // state groups of 16 columns (B = 16, 32, 64)
@@ -789,8 +806,16 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
             }
             if (with_nl && nl->nnlpts > 0) {
                 dim3 gn((unsigned)((nl->nnlpts * B + 255) / 256), (nblk + 3) / 4);
-                hipLaunchKernelGGL((nl_add_kernel<T>), gn, dim3(256), 0, st, nl->nl_pts.as<int32_t>(), nl->nnlpts,
-                                   ptp, eat, egm, dp, hpsi, g->np, B, nat, nblk);
+#define RS_NLADD(NPJ)                                                                                   \
+    case NPJ:                                                                                           \
+        hipLaunchKernelGGL((nl_add_kernel<T, NPJ>), gn, dim3(256), 0, st, nl->nl_pts.as<int32_t>(),     \
+                           nl->nnlpts, ptp, eat, egm, dp, hpsi, g->np, B, nat, nblk);                   \
+        break;
+                switch (npj) {
+                    RS_NLADD(1) RS_NLADD(4) RS_NLADD(9) RS_NLADD(16)
+                    default: return fail(RS_EINVAL, "stencil: unsupported projector count");
+                }
+#undef RS_NLADD
                 RS_HIP(hipGetLastError());
             }
             return RS_OK;
@@ -814,12 +839,12 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
             hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZF, true, R>), grid, dim3(256), 0, st,     \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
                                vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
-                               dp, nat);                                                          \
+                               dp, nat, npj);                                                     \
         else                                                                                       \
             hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZS, false, R>), grid, dim3(256), 0, st,    \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
                                vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
-                               dp, nat);                                                          \
+                               dp, nat, npj);                                                     \
         break;
         switch (B) {
             RS_HPSI(1) RS_HPSI(2) RS_HPSI(4) RS_HPSI(8) RS_HPSI(16) RS_HPSI(32) RS_HPSI(64)
@@ -855,6 +880,17 @@ rs_status check_fields(const rs_grid *g, const rs_nl *nl, int nblk, int B, int d
     return RS_OK;
 }
 
+// Complex states under a real operator: a block of B complex states is the
+// block of 2B real columns (re, im interleaved) in the same memory; the
+// real dtype and column count replace the complex ones.
+rs_status real_columns(int32_t &dtype, int32_t &B, const char *who) {
+    if (dtype != RS_C128 && dtype != RS_C64) return RS_OK;
+    if (B > 32) return fail(RS_EINVAL, std::string(who) + ": complex blocks hold at most 32 states");
+    dtype = dtype == RS_C128 ? RS_F64 : RS_F32;
+    B *= 2;
+    return RS_OK;
+}
+
 }  // namespace
 }  // namespace rs
 
@@ -863,7 +899,9 @@ using namespace rs;
 extern "C" rs_status rs_hpsi_block(const rs_grid *g, const rs_nl *nl, const void *vloc,
                                    const void *psi, void *hpsi, int32_t nblk, int32_t B,
                                    int32_t dtype, void *stream) {
-    rs_status st = check_fields(g, nl, nblk, B, dtype, "rs_hpsi_block");
+    rs_status st = real_columns(dtype, B, "rs_hpsi_block");
+    if (st) return st;
+    st = check_fields(g, nl, nblk, B, dtype, "rs_hpsi_block");
     if (st) return st;
     if (!vloc || !psi || !hpsi) return fail(RS_EINVAL, "rs_hpsi_block: null field pointer");
     if (psi == hpsi) return fail(RS_EINVAL, "rs_hpsi_block: psi and hpsi must not alias");
@@ -875,7 +913,9 @@ extern "C" rs_status rs_hpsi_block(const rs_grid *g, const rs_nl *nl, const void
 
 extern "C" rs_status rs_project_nl(const rs_grid *g, const rs_nl *nl, const void *psi, void *proj,
                                    int32_t nblk, int32_t B, int32_t dtype, void *stream) {
-    rs_status st = check_fields(g, nl, nblk, B, dtype, "rs_project_nl");
+    rs_status st = real_columns(dtype, B, "rs_project_nl");
+    if (st) return st;
+    st = check_fields(g, nl, nblk, B, dtype, "rs_project_nl");
     if (st) return st;
     if (!nl || !psi || !proj) return fail(RS_EINVAL, "rs_project_nl: null argument");
     hipStream_t s = (hipStream_t)stream;
@@ -886,7 +926,9 @@ extern "C" rs_status rs_project_nl(const rs_grid *g, const rs_nl *nl, const void
 
 extern "C" rs_status rs_apply_nl(const rs_grid *g, const rs_nl *nl, const void *proj, void *hpsi,
                                  int32_t nblk, int32_t B, int32_t dtype, void *stream) {
-    rs_status st = check_fields(g, nl, nblk, B, dtype, "rs_apply_nl");
+    rs_status st = real_columns(dtype, B, "rs_apply_nl");
+    if (st) return st;
+    st = check_fields(g, nl, nblk, B, dtype, "rs_apply_nl");
     if (st) return st;
     if (!nl || !proj || !hpsi) return fail(RS_EINVAL, "rs_apply_nl: null argument");
     if (nl->nat == 0) return RS_OK;
@@ -895,11 +937,11 @@ extern "C" rs_status rs_apply_nl(const rs_grid *g, const rs_nl *nl, const void *
     if (dtype == RS_F64)
         hipLaunchKernelGGL((nl_apply_kernel<double>), grid, dim3(256), 0, s, nl->pt_ptr.as<int32_t>(),
                            nl->ent_atom.as<int32_t>(), (const double *)nl->ent_gamma64.p,
-                           nl->d_D.as<double>(), (const double *)proj, (double *)hpsi, g->np, B, nl->nat);
+                           nl->d_D.as<double>(), (const double *)proj, (double *)hpsi, g->np, B, nl->nat, nl->npj);
     else
         hipLaunchKernelGGL((nl_apply_kernel<float>), grid, dim3(256), 0, s, nl->pt_ptr.as<int32_t>(),
                            nl->ent_atom.as<int32_t>(), (const float *)nl->ent_gamma32.p,
-                           nl->d_D.as<double>(), (const float *)proj, (float *)hpsi, g->np, B, nl->nat);
+                           nl->d_D.as<double>(), (const float *)proj, (float *)hpsi, g->np, B, nl->nat, nl->npj);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }

@@ -133,28 +133,30 @@ struct rs_grid {
 struct rs_nl {
     bool host_only = false;
     int nat = 0;
+    int lmax = 1;
+    int npj = 4;                    // projectors per atom, (lmax+1)^2
     int max_states = 0;
     double dv = 0;
     std::vector<int64_t> sph_ptr;   // [nat+1]
     std::vector<int64_t> sph_idx;   // [nnz]
-    std::vector<double> gamma;      // [nnz][4]
+    std::vector<double> gamma;      // [nnz][npj]
     std::vector<int32_t> colour;    // [nat]
-    std::vector<double> D;          // [nat][4]
+    std::vector<double> D;          // [nat][npj]
     int ncolours = 0;
     // projection work split: chunks of sphere entries
     int nchunks = 0;
     rs::DevBuf chunk_atom, chunk_beg, chunk_end, atom_chunk0;  // int32
     rs::DevBuf d_sph_idx;                                       // int32 [nnz]
-    rs::DevBuf d_gamma64, d_gamma32;                            // [nnz][4]
-    rs::DevBuf d_D;                                             // double [nat][4]
+    rs::DevBuf d_gamma64, d_gamma32;                            // [nnz][npj]
+    rs::DevBuf d_D;                                             // double [nat][npj]
     // point-centric table for the fused apply
     rs::DevBuf pt_ptr;                                          // int32 [np+1]
     rs::DevBuf ent_atom;                                        // int32 [nent]
-    rs::DevBuf ent_gamma64, ent_gamma32;                        // [nent][4]
+    rs::DevBuf ent_gamma64, ent_gamma32;                        // [nent][npj]
     rs::DevBuf brick_nl;                                        // int32 [nbricks]
     rs::DevBuf nl_pts;                                          // int32 [nnlpts]
     int64_t nnlpts = 0;
     // scratch
-    rs::DevBuf partial;   // double [max_states][nchunks][4]
-    rs::DevBuf dp;        // dtype  [max_states][nat][4]  (D * projection)
+    rs::DevBuf partial;   // double [max_states][nchunks][npj]
+    rs::DevBuf dp;        // dtype  [max_states][nat][npj]  (D * projection)
 };

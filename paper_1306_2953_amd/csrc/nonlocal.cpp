@@ -1,5 +1,7 @@
 // Host construction of the Kleinman-Bylander projector set (eq. (6),
-// Sec. 5.3): per-atom sphere point lists, projector values, colour groups,
+// Sec. 5.3): per-atom sphere point lists, the values of the (l_max+1)^2
+// projectors gamma_lm = N_l r^l Y_lm exp(-r^2 / 2 sigma^2) (real spherical
+// harmonics, l = 0..l_max <= 3), colour groups,
 // the chunked work list of the projection kernel and the point-centric table
 // of the fused apply.  Built with -ffp-contract=off so that sphere
 // membership, |r_p - R_A|^2 = ((dx*dx + dy*dy) + dz*dz) <= rc*rc, is decided
@@ -16,30 +18,86 @@ constexpr int kChunk = 512;   // sphere entries per projection work-group
 
 double min_image(double d, double L) { return d - L * std::nearbyint(d / L); }
 
+// Projector values at displacement d (r2 = |d|^2 formed as (dx dx + dy dy)
+// + dz dz, e = exp(-r2 / 2 sigma^2)) into out[(lmax+1)^2]: l ascending; l = 1
+// in the order x, y, z; l = 2: xy, yz, 3z^2 - r^2, xz, x^2 - y^2; l = 3:
+// y(3x^2 - y^2), xyz, y(5z^2 - r^2), z(5z^2 - 3r^2), x(5z^2 - r^2),
+// z(x^2 - y^2), x(x^2 - 3y^2).  nrm[l] = N_l times the harmonic's
+// constant is applied per function; l <= 1 uses N_s and N_p directly.
+struct ProjectorShape {
+    int lmax;
+    double ns, npn;      // N_0 Y_00 and N_1 sqrt(3 / 4 pi)
+    double c2[3];        // N_2 times 1/2 sqrt(15/pi), 1/4 sqrt(5/pi), 1/4 sqrt(15/pi)
+    double c3[5];        // N_3 times 1/4 sqrt(35/2pi), 1/2 sqrt(105/pi), 1/4 sqrt(21/2pi),
+                         //           1/4 sqrt(7/pi), 1/4 sqrt(105/pi)
+
+    ProjectorShape(int lmax_, double sigma) : lmax(lmax_) {
+        const double pi = 3.14159265358979323846;
+        ns = 1.0 / std::sqrt(std::pow(pi, 1.5) * sigma * sigma * sigma);
+        npn = 1.0 / std::sqrt(std::pow(pi, 1.5) * std::pow(sigma, 5) / 2.0);
+        // N_l = (Gamma(l + 3/2) sigma^(2l+3) / 2)^(-1/2)
+        const double n2 = 1.0 / std::sqrt(std::tgamma(3.5) * std::pow(sigma, 7) / 2.0);
+        const double n3 = 1.0 / std::sqrt(std::tgamma(4.5) * std::pow(sigma, 9) / 2.0);
+        c2[0] = n2 * 0.5 * std::sqrt(15.0 / pi);
+        c2[1] = n2 * 0.25 * std::sqrt(5.0 / pi);
+        c2[2] = n2 * 0.25 * std::sqrt(15.0 / pi);
+        c3[0] = n3 * 0.25 * std::sqrt(35.0 / (2.0 * pi));
+        c3[1] = n3 * 0.5 * std::sqrt(105.0 / pi);
+        c3[2] = n3 * 0.25 * std::sqrt(21.0 / (2.0 * pi));
+        c3[3] = n3 * 0.25 * std::sqrt(7.0 / pi);
+        c3[4] = n3 * 0.25 * std::sqrt(105.0 / pi);
+    }
+
+    void eval(const double d[3], double r2, double e, double *out) const {
+        const double x = d[0], y = d[1], z = d[2];
+        out[0] = ns * e;
+        if (lmax < 1) return;
+        out[1] = npn * x * e;
+        out[2] = npn * y * e;
+        out[3] = npn * z * e;
+        if (lmax < 2) return;
+        out[4] = c2[0] * x * y * e;
+        out[5] = c2[0] * y * z * e;
+        out[6] = c2[1] * (3.0 * z * z - r2) * e;
+        out[7] = c2[0] * x * z * e;
+        out[8] = c2[2] * (x * x - y * y) * e;
+        if (lmax < 3) return;
+        out[9] = c3[0] * y * (3.0 * x * x - y * y) * e;
+        out[10] = c3[1] * x * y * z * e;
+        out[11] = c3[2] * y * (5.0 * z * z - r2) * e;
+        out[12] = c3[3] * z * (5.0 * z * z - 3.0 * r2) * e;
+        out[13] = c3[2] * x * (5.0 * z * z - r2) * e;
+        out[14] = c3[4] * z * (x * x - y * y) * e;
+        out[15] = c3[0] * x * (x * x - 3.0 * y * y) * e;
+    }
+};
+
 }  // namespace
 
 extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *pos,
-                                  const double *D, double rc, double sigma,
+                                  const double *D, double rc, double sigma, int32_t lmax,
                                   int32_t max_states, rs_nl **out) {
     using namespace rs;
     if (!g || !out) return fail(RS_EINVAL, "rs_nl_create: null argument");
     *out = nullptr;
     if (nat < 0 || (nat > 0 && (!pos || !D))) return fail(RS_EINVAL, "rs_nl_create: bad atoms");
     if (!(rc > 0) || !(sigma > 0)) return fail(RS_EINVAL, "rs_nl_create: rc and sigma must be > 0");
+    if (lmax < 0 || lmax > 3) return fail(RS_EINVAL, "rs_nl_create: lmax must be 0..3");
     if (max_states < 1 || max_states > 4096) return fail(RS_EINVAL, "rs_nl_create: max_states out of range");
     auto nl = new (std::nothrow) rs_nl();
     if (!nl) return fail(RS_ENOMEM, "host allocation failed");
     nl->nat = nat;
+    nl->lmax = lmax;
+    nl->npj = (lmax + 1) * (lmax + 1);
+    const int npj = nl->npj;
     nl->max_states = max_states;
     nl->dv = g->h * g->h * g->h;
-    nl->D.assign(D, D + 4 * (size_t)nat);
+    nl->D.assign(D, D + npj * (size_t)nat);
 
     const bool periodic = g->kind == RS_GRID_PERIODIC;
     const double Lbox = periodic ? (double)g->n * g->h : 0.0;
     const double rc2 = rc * rc;
-    const double pi = 3.14159265358979323846;
-    const double ns = 1.0 / std::sqrt(std::pow(pi, 1.5) * sigma * sigma * sigma);
-    const double npn = 1.0 / std::sqrt(std::pow(pi, 1.5) * std::pow(sigma, 5) / 2.0);
+    const ProjectorShape shape(lmax, sigma);
     const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
 
     nl->sph_ptr.assign(nat + 1, 0);
@@ -87,11 +145,10 @@ extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *p
             }
             const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
             const double e = std::exp(-r2 * inv2s2);
+            double val[16];
+            shape.eval(d, r2, e, val);
             nl->sph_idx.push_back(p);
-            nl->gamma.push_back(ns * e);
-            nl->gamma.push_back(npn * d[0] * e);
-            nl->gamma.push_back(npn * d[1] * e);
-            nl->gamma.push_back(npn * d[2] * e);
+            nl->gamma.insert(nl->gamma.end(), val, val + npj);
         }
         nl->sph_ptr[A + 1] = (int64_t)nl->sph_idx.size();
     }
@@ -137,13 +194,13 @@ extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *p
     for (int64_t p = 0; p < g->np; ++p) cnt[p + 1] += cnt[p];
     std::vector<int32_t> fillpos(cnt.begin(), cnt.end() - 1);
     std::vector<int32_t> ent_atom(nnz);
-    std::vector<double> ent_g(4 * nnz);
+    std::vector<double> ent_g(npj * nnz);
     for (int A = 0; A < nat; ++A)
         for (int64_t e = nl->sph_ptr[A]; e < nl->sph_ptr[A + 1]; ++e) {
             const int64_t p = nl->sph_idx[e];
             const int32_t k = fillpos[p]++;
             ent_atom[k] = A;
-            for (int i = 0; i < 4; ++i) ent_g[4 * (int64_t)k + i] = nl->gamma[4 * e + i];
+            for (int i = 0; i < npj; ++i) ent_g[npj * (int64_t)k + i] = nl->gamma[npj * e + i];
         }
     std::vector<int32_t> brick_nl(std::max<int64_t>(g->nbricks, 1), 0);
     if (g->kernels_ok)
@@ -184,8 +241,8 @@ extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *p
     if (!st) st = nl->ent_gamma32.upload(eg32);
     if (!st) st = nl->brick_nl.upload(brick_nl);
     if (!st) st = nl->nl_pts.upload(nl_pts);
-    if (!st) st = nl->partial.alloc(sizeof(double) * 4 * (size_t)max_states * std::max(nl->nchunks, 1));
-    if (!st) st = nl->dp.alloc(sizeof(double) * 4 * (size_t)max_states * std::max(nat, 1));
+    if (!st) st = nl->partial.alloc(sizeof(double) * npj * (size_t)max_states * std::max(nl->nchunks, 1));
+    if (!st) st = nl->dp.alloc(sizeof(double) * npj * (size_t)max_states * std::max(nat, 1));
     if (st) { delete nl; return st; }
     *out = nl;
     return RS_OK;
@@ -193,10 +250,11 @@ extern "C" rs_status rs_nl_create(const rs_grid *g, int32_t nat, const double *p
 
 extern "C" void rs_nl_destroy(rs_nl *nl) { delete nl; }
 
-extern "C" rs_status rs_nl_info(const rs_nl *nl, int64_t *nnz, int32_t *ncolours) {
+extern "C" rs_status rs_nl_info(const rs_nl *nl, int64_t *nnz, int32_t *ncolours, int32_t *nproj) {
     if (!nl) return rs::fail(RS_EINVAL, "rs_nl_info: null handle");
     if (nnz) *nnz = (int64_t)nl->sph_idx.size();
     if (ncolours) *ncolours = nl->ncolours;
+    if (nproj) *nproj = nl->npj;
     return RS_OK;
 }
 

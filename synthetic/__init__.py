@@ -148,6 +148,19 @@ def draw_atoms(w: Workload, rng: Optional[np.random.Generator] = None) -> Atoms:
     return Atoms(pos=pos, depth=depth, width=width, D=D)
 
 
+def couplings_lmax(w: Workload, atoms: Atoms, lmax: int) -> np.ndarray:
+    """KB couplings for projectors up to lmax, [nat, (lmax+1)^2]: the
+    workload's s and p values, then one value per atom and l >= 2 shared by
+    its 2l + 1 projectors, drawn U(0.3, 1.0) Ha from default_rng(seed + 7)."""
+    nat = atoms.D.shape[0]
+    cols = [atoms.D[:, :1]] + ([atoms.D[:, 1:4]] if lmax >= 1 else [])
+    rng = np.random.default_rng(w.seed + 7)
+    for l in range(2, lmax + 1):
+        d = rng.uniform(0.3, 1.0, size=nat)
+        cols.append(np.repeat(d[:, None], 2 * l + 1, axis=1))
+    return np.concatenate(cols, axis=1)
+
+
 def draw_states(rng: np.random.Generator, nstates: int, npoints: int,
                 dtype=np.float64) -> np.ndarray:
     """Initial states, uniform[-1, 1], state-major [nstates, npoints]."""

@@ -133,3 +133,47 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "--gpus must be 1" in msg["error"]
+
+
+@pytest.mark.parametrize("lmax", [0, 2, 3])
+def test_projector_sets_lmax_match_oracle(lmax):
+    """(lmax+1)^2 projectors per atom: the same sphere lists, and projector
+    values within a few ulps of the oracle's (the constants are folded in a
+    different order), for a sphere and a periodic box."""
+    for name, cfg in (("sphere_r12_h0.2", dict(radius=4.0, nat=5, atom_radius=2.5)),
+                      ("periodic96_h0.25", dict(n=24, nat=6))):
+        w = synthetic.make_workload(name, **cfg)
+        og = ogrid.grid_for(w)
+        atoms = synthetic.draw_atoms(w)
+        npj = (lmax + 1) ** 2
+        D = np.random.default_rng(40 + lmax).uniform(0.2, 2.0, size=(atoms.pos.shape[0], npj))
+        ops = okb.build_projectors(og, atoms.pos, D, w.rc, w.sigma, lmax=lmax)
+        g = rsd.Grid.for_workload(w, host_only=True)
+        nl = rsd.NonLocal(g, atoms.pos, D, w.rc, w.sigma, max_states=64, lmax=lmax)
+        assert nl.nproj == npj
+        ex = nl.export()
+        assert np.array_equal(ex["sph_idx"], np.concatenate(ops.idx))
+        gam = np.concatenate(ops.gamma)
+        assert ex["gamma"].shape == gam.shape
+        assert np.max(np.abs(ex["gamma"] - gam)) <= 1e-14 * np.max(np.abs(gam))
+        assert np.array_equal(ex["colour"], ops.colour)
+
+
+def test_projector_set_refuses_bad_lmax_and_D():
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=3.0, nat=2, atom_radius=1.0)
+    atoms = synthetic.draw_atoms(w)
+    g = rsd.Grid.for_workload(w, host_only=True)
+    with pytest.raises(ValueError):
+        rsd.NonLocal(g, atoms.pos, np.ones((2, 25)), w.rc, w.sigma, max_states=8, lmax=4)
+    with pytest.raises(ValueError):
+        rsd.NonLocal(g, atoms.pos, np.ones((2, 4)), w.rc, w.sigma, max_states=8, lmax=2)
+    # the C ABI refuses lmax outside 0..3 on its own
+    import ctypes
+    h = ctypes.c_void_p()
+    pos = np.ascontiguousarray(atoms.pos)
+    D = np.ones(2 * 25)
+    L = _abi.lib()
+    rc = L.rs_nl_create(g.handle, 2, pos.ctypes.data_as(ctypes.c_void_p), D.ctypes.data_as(ctypes.c_void_p),
+                        float(w.rc), float(w.sigma), 4, 8, ctypes.byref(h))
+    assert rc == _abi.RS_EINVAL and not h.value
+    assert b"lmax" in L.rs_last_error()

@@ -56,12 +56,46 @@ def test_field_shape_dtype_and_block(grid):
 
 def test_projection_buffers(grid):
     class NL:
-        nat, handle = 3, None
+        nat, nproj, max_states, handle = 3, 4, 64, None
     n = grid.np
     with pytest.raises(ValueError, match="proj must have shape"):
         rsd.project_nl(grid, NL, f64(2, n, 8), f64(2, 3, 4, 4))
     with pytest.raises(ValueError, match="proj must be torch.float64"):
         rsd.apply_nl(grid, NL, torch.zeros(2, 3, 4, 8), f64(2, n, 8))
+
+    class NL16(NL):
+        nproj = 16
+    with pytest.raises(ValueError, match=r"proj must have shape \(2, 3, 16, 8\)"):
+        rsd.project_nl(grid, NL16, f64(2, n, 8), f64(2, 3, 4, 8))
+    # complex states: two real columns each, at most 32 per block
+    c128 = torch.zeros(2, n, 32, dtype=torch.complex128)
+    with pytest.raises(ValueError, match="real columns exceed"):
+        rsd.project_nl(grid, NL, c128, torch.zeros(2, 3, 4, 32, dtype=torch.complex128))
+    with pytest.raises(ValueError, match=r"power of two in \[1, 32\]"):
+        rsd.project_nl(grid, NL, torch.zeros(1, n, 64, dtype=torch.complex128),
+                       torch.zeros(1, 3, 4, 64, dtype=torch.complex128))
+    with pytest.raises(ValueError, match="proj must be torch.complex64"):
+        rsd.project_nl(grid, NL, torch.zeros(1, n, 8, dtype=torch.complex64), f64(1, 3, 4, 8))
+
+
+def test_complex_fields(grid):
+    n = grid.np
+    z = torch.zeros(1, n, 8, dtype=torch.complex128)
+    with pytest.raises(ValueError, match="vloc must be torch.float64"):
+        rsd.hpsi_block(grid, None, torch.zeros(n, dtype=torch.complex128), z, torch.zeros_like(z))
+    with pytest.raises(ValueError, match="device tensor"):
+        rsd.hpsi_block(grid, None, f64(n), z, torch.zeros_like(z))
+    c = _ctx(grid, max_states=16)
+    with pytest.raises(ValueError, match="real columns exceed"):
+        c.overlap(torch.zeros(2, n, 8, dtype=torch.complex128), torch.zeros(2, n, 8, dtype=torch.complex128))
+    c = _ctx(grid, max_states=64)
+    with pytest.raises(ValueError, match="S must be torch.complex128"):
+        c.overlap(z, z, S=f64(8, 8))
+    # only H psi, the projections and the overlap take complex states
+    with pytest.raises(ValueError, match="float32 or float64, got"):
+        c.rotate(z, f64(8, 8))
+    with pytest.raises(ValueError, match="float32 or float64, got"):
+        rsd.overlap_noalloc(grid, z, z, f64(8, 8))
 
 
 def test_context_refusals(grid):
