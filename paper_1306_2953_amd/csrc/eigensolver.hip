@@ -76,6 +76,33 @@ template <typename T> struct OpAxpy2Dots {
         a[1] += (double)yv * (double)hv;
     }
 };
+// The first DIIS pass over iterates 0 and 1 with iterate 1 formed on the
+// fly: y = x + lambda d, hy = hx + lambda hd (stored, rounded to T, for the
+// later passes), and the DIIS matrices of {x, y} as OpDiis<T, 2> forms them
+// from the stored values.  eps[N + c] (iterate 1's Rayleigh quotient) comes
+// from the trial-step dots, so no separate pass writes iterate 1.
+template <typename T> struct OpDiis2New {
+    const T *x, *hx, *d, *hd;
+    T *y, *hy;
+    const double *lam, *eps;
+    int N;
+    __device__ void operator()(int64_t i, int c, double *a) const {
+        const double l = lam[c];
+        const double u = x[i], hu = hx[i];
+        const T yv = (T)(u + l * (double)d[i]);
+        const T hv = (T)(hu + l * (double)hd[i]);
+        y[i] = yv;
+        hy[i] = hv;
+        const double xl = yv, rl = (double)hv - eps[N + c] * xl;
+        const double e1 = u - xl, r1 = (hu - eps[c] * u) - rl;
+        a[0] += rl * rl;
+        a[1] += rl * r1;
+        a[2] += r1 * r1;
+        a[3] += xl * xl;
+        a[4] += xl * e1;
+        a[5] += e1 * e1;
+    }
+};
 template <typename T> struct OpResid {   // R = h - eps x, <R|R>
     const T *x, *h;
     T *R;
@@ -309,6 +336,19 @@ __global__ void lambda_kernel(const double *__restrict__ d2, const double *__res
         if (lowest_geneig(2, A, Bm, v) && v[0] != 0.0) l = v[1] / v[0] * s;
     }
     lam[c] = l;
+}
+
+// Rayleigh quotient of iterate 1 = x + lambda d from the trial-step dots:
+// (<x|Hx> + lambda (<x|Hd> + <d|Hx>) + lambda^2 <d|Hd>) /
+// (<x|x> + 2 lambda <x|d> + lambda^2 <d|d>).
+__global__ void eps1_kernel(const double *__restrict__ d2, const double *__restrict__ d5,
+                            const double *__restrict__ lam, int N, double *__restrict__ eps1) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const double l = lam[c];
+    const double num = d2[1 * N + c] + l * (d5[0 * N + c] + d5[1 * N + c]) + l * l * d5[2 * N + c];
+    const double den = d2[0 * N + c] + 2.0 * l * d5[3 * N + c] + l * l * d5[4 * N + c];
+    eps1[c] = den > 0.0 ? num / den : 0.0;
 }
 
 // Filter and network coefficients of the trial step (state frozen: lambda
@@ -619,19 +659,31 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
         RS_HIP(hipGetLastError());
         return RS_OK;
     }
-    // iterate 1 and its dots [<x|x>, <x|Hx>] in one pass
-    if ((e = colreduce<2>(OpAxpy2Dots<T>{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->hx[1].as<T>(),
-                                        S->hh[1].as<T>(), S->lam.as<double>()},
-                          np, B, nblk, dv, partial, S->d2.as<double>(), st)))
+    // iterate 1: with the filter alone its Rayleigh quotient follows from
+    // the trial-step dots and the first DIIS pass writes it; with a network
+    // (mixed directions) a pass of its own writes it and its dots
+    const bool fused1 = !S->cnn;
+    if (fused1) {
+        hipLaunchKernelGGL(eps1_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d5.as<double>(),
+                           S->lam.as<double>(), N, S->eps.as<double>() + N);
+    } else if ((e = colreduce<2>(OpAxpy2Dots<T>{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->hx[1].as<T>(),
+                                               S->hh[1].as<T>(), S->lam.as<double>()},
+                                 np, B, nblk, dv, partial, S->d2.as<double>(), st))) {
         return e;
+    }
     xs[1] = S->hx[1].as<T>();
     hs[1] = S->hh[1].as<T>();
     for (int n = 2; n <= m; ++n) {
         // 4. DIIS iteration over the n iterates 0..n-1: eps of the newest
         // (its dots were accumulated when it was written)
-        hipLaunchKernelGGL(eps_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N,
-                           S->eps.as<double>() + (int64_t)(n - 1) * N);
-        if (n == 2) {
+        if (n > 2 || !fused1)
+            hipLaunchKernelGGL(eps_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), N,
+                               S->eps.as<double>() + (int64_t)(n - 1) * N);
+        if (n == 2 && fused1) {
+            OpDiis2New<T> op{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->hx[1].as<T>(), S->hh[1].as<T>(),
+                             S->lam.as<double>(), S->eps.as<double>(), N};
+            if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
+        } else if (n == 2) {
             OpDiis<T, 2> op{{xs[0], xs[1]}, {hs[0], hs[1]}, S->eps.as<double>(), N};
             if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
         } else {
@@ -655,7 +707,9 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
                                S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N);
         RS_HIP(hipGetLastError());
         if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), st))) return e;
-        if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
+        // H d only where another DIIS iteration follows: the last update
+        // needs d alone
+        if (n < m && (e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
         if (n < m) {
             if ((e = colreduce<2>(OpAxpy2Dots<T>{xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb, S->lam.as<double>()},
                                   np, B, nblk, dv, partial, S->d2.as<double>(), st)))
