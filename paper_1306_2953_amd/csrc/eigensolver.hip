@@ -190,7 +190,8 @@ axpy1_kernel(const T *__restrict__ x, const T *__restrict__ d, T *y, const doubl
     y[i] = (T)((double)x[i] + lam[c] * (double)d[i]);
 }
 
-// psi_bar = sum_a c_a e_a, H psi_bar = sum_a c_a he_a, R_bar = sum_a c_a r_a
+// psi_bar = sum_a c_a e_a, H psi_bar = sum_a c_a he_a (skipped when hb is
+// null), R_bar = sum_a c_a r_a
 template <typename T> struct Hist {
     const T *x[kMaxHist], *h[kMaxHist];
 };
@@ -218,7 +219,7 @@ combine_kernel(Hist<T> H, const double *__restrict__ eps, const double *__restri
         sr += ck * ((hk - eps[k * N + c] * xk) - rl);
     }
     xb[i] = (T)sx;
-    hb[i] = (T)sh;
+    if (hb != nullptr) hb[i] = (T)sh;
     rb[i] = (T)sr;
 }
 
@@ -692,8 +693,9 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
         }
         hipLaunchKernelGGL(diis_kernel, dim3(gs), dim3(64), 0, st, S->mats.as<double>(), n, S->lam.as<double>(), N,
                            S->coef.as<double>());
-        // psi_bar, H psi_bar into slot n; R_bar into R
-        T *xb = S->hx[n].as<T>(), *hb = S->hh[n].as<T>();
+        // psi_bar, H psi_bar into slot n; R_bar into R.  The last iteration
+        // needs no H psi_bar (nothing follows that would use it)
+        T *xb = S->hx[n].as<T>(), *hb = n < m ? S->hh[n].as<T>() : nullptr;
         Hist<T> hist{};
         for (int i = 0; i < n; ++i) {
             hist.x[i] = xs[i];
