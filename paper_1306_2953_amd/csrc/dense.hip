@@ -936,6 +936,64 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                 rot[((int64_t)sweep * (M - 1) + r) * h + k] = make_double2(c, s);
             }
             __syncthreads();
+            if (h <= 64 && nw == 16) {
+                // N <= 128: a lane owns at most the four blocks (k, l) with
+                // k = wave + 16 j, l = k + lane.  A round reads only blocks
+                // l >= k and every thread writes only its own blocks and
+                // their mirrors, so all four blocks are loaded before any is
+                // stored (the loads of a round then overlap in LDS)
+                double x[4][4];
+                int i4[4][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = wave + 16 * j, l = k + lane;
+                    if (!(k < h && l < h)) continue;
+                    const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
+                    i4[j][0] = pk; i4[j][1] = qk; i4[j][2] = pl; i4[j][3] = ql;
+                    x[j][0] = A[pk * ld + pl];
+                    x[j][1] = ql < N ? A[pk * ld + ql] : 0.0;
+                    x[j][2] = qk < N ? A[qk * ld + pl] : 0.0;
+                    x[j][3] = qk < N && ql < N ? A[qk * ld + ql] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = wave + 16 * j, l = k + lane;
+                    if (!(k < h && l < h)) continue;
+                    const int pk = i4[j][0], qk = i4[j][1], pl = i4[j][2], ql = i4[j][3];
+                    const bool vk = qk < N, vl = ql < N;
+                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+                    const double x00 = x[j][0], x01 = x[j][1], x10 = x[j][2], x11 = x[j][3];
+                    const double y00 = cl * x00 - sl * x01, y01 = sl * x00 + cl * x01;
+                    const double y10 = cl * x10 - sl * x11, y11 = sl * x10 + cl * x11;
+                    const double z00 = ck * y00 - sk * y10, z01 = ck * y01 - sk * y11;
+                    const double z10 = sk * y00 + ck * y10, z11 = sk * y01 + ck * y11;
+                    if (l == k) {
+                        A[pk * ld + pk] = z00;
+                        if (vk) {
+                            A[pk * ld + qk] = 0.0;
+                            A[qk * ld + pk] = 0.0;
+                            A[qk * ld + qk] = z11;
+                        }
+                        continue;
+                    }
+                    A[pk * ld + pl] = z00;
+                    A[pl * ld + pk] = z00;
+                    if (vl) {
+                        A[pk * ld + ql] = z01;
+                        A[ql * ld + pk] = z01;
+                    }
+                    if (vk) {
+                        A[qk * ld + pl] = z10;
+                        A[pl * ld + qk] = z10;
+                    }
+                    if (vk && vl) {
+                        A[qk * ld + ql] = z11;
+                        A[ql * ld + qk] = z11;
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
             for (int k = wave; k < h; k += nw) {
                 const int pk = pp[k], qk = qq[k];
                 const bool vk = qk < N;

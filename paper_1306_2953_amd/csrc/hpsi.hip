@@ -524,6 +524,13 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
         load_halo(z + PH, hreg[hs]);
         load_v(z + 2, vreg[(vs + 2) % 3]);
         __syncthreads();
+        const MarchBrick mb = ltab[(z >> 2) * 12 + opos];
+        if constexpr (!FULL) {
+            // a wave holds one 4-point x row of one brick: when none of its
+            // points exists in this plane there is nothing to compute or
+            // store (its zeros are already staged for the neighbours)
+            if (((mb.mask >> ((z & 3) * 16 + (y0 & 3) * 4)) & 0xFull) == 0) return;
+        }
         const unsigned char *L = pl + (y0 * 16 + x0) * RB + s * sizeof(T);   // point (x0 - 4, y0 - 4)
         auto at = [&](int dx, int dy) -> T { return *(const T *)(L + ((dy + 4) * 16 + dx + 4) * RB); };
         // c0 v + sum_m c_m (v_-m + v_+m) per axis, c_m = W_(m-1) - W_m
@@ -538,7 +545,6 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
             sum += cc[m] * (win[(c0 + kMW - m) % kMW] + win[(c0 + m) % kMW]);
         }
         const T acc = pre * sum + (vreg[vs] + vconst) * win[c0];
-        const MarchBrick mb = ltab[(z >> 2) * 12 + opos];
         if (FULL || mb.id >= 0) bstore<T>(acc, rh, roff(prow(mb, (z & 3) * 16 + oq), loff, ROWB));
     };
     int zb = 4;
