@@ -180,7 +180,7 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
           uint32_t lane_off, const uint32_t *tbl, const T *__restrict__ vloc, T vconst, T pre, T w0,
           T w1, T w2, T w3, const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
           const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
-          const T *__restrict__ dpl, int npj, int B) {
+          const T *__restrict__ dpl, int B) {
     constexpr int NP = 16 * NZ;
     Slots<T, ROW, FAST> nb[6], me;
 #pragma unroll
@@ -262,10 +262,10 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
         const T vp = vloc == nullptr ? vconst : (me.has(q) ? vloc[me.point(q)] : T(0));
         acc[k] = pre * acc[k] + vp * own[k];
     }
-    // non-local part 2, point-centric: sum over the atoms whose sphere holds
-    // the point of gamma_A,i(p) * (D_A,i P_A,i,s), i < npj
+    // non-local part 2 for the s and p set (4 projectors per atom; other
+    // projector counts are added by nl_add_kernel), point-centric: sum over
+    // the atoms whose sphere holds the point of gamma_A,i(p) * (D_A,i P_A,i,s)
     if (brick_nl != nullptr && brick_nl[b]) {
-        const int dps = npj * B;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const int q = Z0 * 16 + k;
@@ -273,15 +273,9 @@ hpsi_wave(const BrickRec &br, const BrickRec *__restrict__ bricks, int b, rsrc_t
                 const int p = me.point(q);
                 const int e1 = pt_ptr[p + 1];
                 for (int e = pt_ptr[p]; e < e1; ++e) {
-                    const T *g = ent_gamma + npj * (int64_t)e;
-                    const T *d = dpl + ent_atom[e] * dps;
-                    if (npj == 4) {
-                        acc[k] += g[0] * d[0] + g[1] * d[B] + g[2] * d[2 * B] + g[3] * d[3 * B];
-                    } else {
-                        T t = g[0] * d[0];
-                        for (int i = 1; i < npj; ++i) t += g[i] * d[i * B];
-                        acc[k] += t;
-                    }
+                    const T *g = ent_gamma + 4 * (int64_t)e;
+                    const T *d = dpl + ent_atom[e] * 4 * B;
+                    acc[k] += g[0] * d[0] + g[1] * d[B] + g[2] * d[2 * B] + g[3] * d[3 * B];
                 }
             }
         }
@@ -305,7 +299,7 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
                   T pre, T w0, T w1, T w2, T w3,
                   const int32_t *__restrict__ brick_nl, const int32_t *__restrict__ pt_ptr,
                   const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma,
-                  const T *__restrict__ dp, int nat, int npj) {
+                  const T *__restrict__ dp, int nat) {
     constexpr int PARTS = 4 / NZ;
     constexpr int ROW = B * (int)sizeof(T);
     __shared__ uint32_t tbl_all[FAST ? 1 : 4 * 7 * 64];
@@ -348,11 +342,11 @@ hpsi_brick_kernel(const BrickRec *__restrict__ bricks, const int32_t *__restrict
     const rsrc_t rp = make_rsrc(psi + blk0 * blk_elems, bytes);
     const rsrc_t rh = make_rsrc(hpsi + blk0 * blk_elems, bytes);
     const uint32_t lane_off = (uint32_t)(((blk - blk0) * blk_elems + s) * sizeof(T));
-    const T *dpl = dp ? dp + (int64_t)blk * nat * npj * B + s : nullptr;
+    const T *dpl = dp ? dp + (int64_t)blk * nat * 4 * B + s : nullptr;
     const BrickRec br = bricks[b];
 #define RS_PART(ZZ)                                                                            \
     hpsi_wave<T, ROW, NZ, ZZ, FAST, R>(br, bricks, b, rp, rh, lane_off, tbl, vloc, vconst, pre, w0, w1, w2, w3, \
-                                    brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, npj, B)
+                                    brick_nl, pt_ptr, ent_atom, ent_gamma, dpl, B)
     if (part == 0) RS_PART(0);
     if constexpr (PARTS >= 2) { if (part == 1) RS_PART(NZ); }
     if constexpr (PARTS == 4) { if (part == 2) RS_PART(2 * NZ); if (part == 3) RS_PART(3 * NZ); }
@@ -750,6 +744,28 @@ rs_status launch_project(const rs_grid *g, const rs_nl *nl, const T *psi, T *pro
     return RS_OK;
 }
 
+// The projector term added to a finished H psi (nl_add_kernel), for the
+// set's projector count; the projections must be in nl->dp.
+template <typename T>
+rs_status launch_nl_add(const rs_grid *g, const rs_nl *nl, T *hpsi, int nblk, int B, hipStream_t st) {
+    if (nl->nnlpts == 0) return RS_OK;
+    const T *egm = sizeof(T) == 8 ? (const T *)nl->ent_gamma64.p : (const T *)nl->ent_gamma32.p;
+    dim3 gn((unsigned)((nl->nnlpts * B + 255) / 256), (nblk + 3) / 4);
+#define RS_NLADD(NPJ)                                                                                   \
+    case NPJ:                                                                                           \
+        hipLaunchKernelGGL((nl_add_kernel<T, NPJ>), gn, dim3(256), 0, st, nl->nl_pts.as<int32_t>(),     \
+                           nl->nnlpts, nl->pt_ptr.as<int32_t>(), nl->ent_atom.as<int32_t>(), egm,       \
+                           (const T *)nl->dp.p, hpsi, g->np, B, nl->nat, nblk);                         \
+        break;
+    switch (nl->npj) {
+        RS_NLADD(1) RS_NLADD(4) RS_NLADD(9) RS_NLADD(16)
+        default: return fail(RS_EINVAL, "stencil: unsupported projector count");
+    }
+#undef RS_NLADD
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
 // Applies out = pre * L psi + V psi (+ V_nl psi when nl is given), L the
 // star stencil with first-difference weights w0..w3 (see line_lap); V is
 // vloc, or the constant vconst when vloc is null.  R = 1: nearest
@@ -810,24 +826,14 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
 #undef RS_MARCH_LAUNCH
                 RS_HIP(hipGetLastError());
             }
-            if (with_nl && nl->nnlpts > 0) {
-                dim3 gn((unsigned)((nl->nnlpts * B + 255) / 256), (nblk + 3) / 4);
-#define RS_NLADD(NPJ)                                                                                   \
-    case NPJ:                                                                                           \
-        hipLaunchKernelGGL((nl_add_kernel<T, NPJ>), gn, dim3(256), 0, st, nl->nl_pts.as<int32_t>(),     \
-                           nl->nnlpts, ptp, eat, egm, dp, hpsi, g->np, B, nat, nblk);                   \
-        break;
-                switch (npj) {
-                    RS_NLADD(1) RS_NLADD(4) RS_NLADD(9) RS_NLADD(16)
-                    default: return fail(RS_EINVAL, "stencil: unsupported projector count");
-                }
-#undef RS_NLADD
-                RS_HIP(hipGetLastError());
-            }
-            return RS_OK;
+            return with_nl ? launch_nl_add<T>(g, nl, hpsi, nblk, B, st) : RS_OK;
         }
     }
-    // interior bricks: NZF planes per wave; surface bricks: NZS
+    // interior bricks: NZF planes per wave; surface bricks: NZS.  The s and
+    // p projector term is fused into the brick kernel; other projector
+    // counts are added afterwards
+    const bool fuse_nl = with_nl && npj == 4;
+    if (!fuse_nl) bnl = nullptr;
     constexpr int NZF = sizeof(T) == 8 ? kNZF64 : kNZF32;
     constexpr int NZS = sizeof(T) == 8 ? kNZS64 : kNZS32;
     for (int pass = 0; pass < 2; ++pass) {
@@ -845,12 +851,12 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
             hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZF, true, R>), grid, dim3(256), 0, st,     \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
                                vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
-                               dp, nat, npj);                                                     \
+                               dp, nat);                                                          \
         else                                                                                       \
             hipLaunchKernelGGL((hpsi_brick_kernel<T, BB, NZS, false, R>), grid, dim3(256), 0, st,    \
                                g->bricks.as<BrickRec>(), ex, (int)nexec, nwg, nwg_pad, psi, hpsi, \
                                vloc, vconst, g->np, nblk, pre, w0, w1, w2, w3, bnl, ptp, eat, egm, \
-                               dp, nat, npj);                                                     \
+                               dp, nat);                                                          \
         break;
         switch (B) {
             RS_HPSI(1) RS_HPSI(2) RS_HPSI(4) RS_HPSI(8) RS_HPSI(16) RS_HPSI(32) RS_HPSI(64)
@@ -858,7 +864,7 @@ rs_status launch_stencil(const rs_grid *g, const rs_nl *nl, const T *vloc, T vco
 #undef RS_HPSI
         RS_HIP(hipGetLastError());
     }
-    return RS_OK;
+    return with_nl && !fuse_nl ? launch_nl_add<T>(g, nl, hpsi, nblk, B, st) : RS_OK;
 }
 
 // The 25-point kinetic stencil of Sec. 5.1: c = (8/5, -1/5, 8/315, -1/560),
