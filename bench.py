@@ -564,6 +564,47 @@ def ordering_study(steps=10):
     return out
 
 
+def cnn_profile(k):
+    """For kernel-trace runs: k applications of the learned preconditioner to
+    the 256 FP32 states of the periodic 96^3 workload (the three 3x3x3
+    convolution layers over the whole box, 2160 multiply-adds per box point
+    and state), then k Adam training steps on batches of 32 random 16^3
+    crops (loss, gradients, update).  Returns per-call times and the
+    forward rate."""
+    import torch
+    import paper_1306_2953_amd as rsd
+    from paper_1306_2953_amd import learned
+    w = synthetic.WORKLOADS["periodic96_h0.25"]
+    g = rsd.Grid.for_workload(w)
+    r = torch.from_numpy(rsd.to_blocks(synthetic.draw_states(synthetic.rng_after_atoms(w), w.nstates, g.np)
+                                       .astype(np.float32), w.block)).cuda()
+    nst = int(r.shape[0]) * w.block
+    sigma = torch.full((nst,), -1.0, dtype=torch.float64, device="cuda")
+    net = rsd.Cnn(max(32, w.block), int(np.prod([g.nb[a] * 4 for a in range(3)])))
+    net.set_params(learned.init_params(0))
+    net_box = net.box(g)
+    stream = torch.cuda.current_stream()
+    net.precondition(g, r, sigma)
+    t_pre = time_calls(lambda: net.precondition(g, r, sigma), k, stream)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    u = torch.randn((32, 16, 16, 16), generator=gen, device="cuda", dtype=torch.float32)
+    t = torch.randn((32, 16, 16, 16), generator=gen, device="cuda", dtype=torch.float32)
+    sig = torch.full((32,), -1.0, dtype=torch.float64, device="cuda")
+    net.train_step(u, t, sig, g.h, 3, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        net.train_step(u, t, sig, g.h, 3, 1e-4)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / k
+    npts = int(np.prod(net_box))
+    flop = 2.0 * 2160 * npts * nst
+    out = {"box": list(net_box), "states": nst, "precondition_s": t_pre, "forward_flop": flop,
+           "forward_tflops": flop / t_pre / 1e12, "train_step_s": t_train}
+    log(f"cnn profile: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -586,6 +627,9 @@ def main():
     ap.add_argument("--profile-eig", type=int, default=0, metavar="K",
                     help="for kernel-trace runs: K eigensolver steps of the FP64 sphere and of "
                          "its FP32 split-precision form from the seeded start; prints step times")
+    ap.add_argument("--profile-cnn", type=int, default=0, metavar="K",
+                    help="for kernel-trace runs: K applications of the learned preconditioner to the "
+                         "periodic workload's 256 states and K training steps; prints the forward rate")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of the FETCH_SIZE and WRITE_SIZE "
                          "passes over --traffic-probe into profiles/hpsi_traffic.json")
@@ -605,6 +649,9 @@ def main():
             wk = synthetic.WORKLOADS[name]
             r = eigensolve_run(wk, dt, wk.block, a.profile_eig, 0.0, log_every=1)
             log(f"{wk.name} {dt}: step times {np.diff([0.0] + r['times'])}")
+        return
+    if a.profile_cnn:
+        print(json.dumps(cnn_profile(a.profile_cnn)), flush=True)
         return
     if a.ordering_study:
         print(json.dumps(ordering_study(a.steps)), flush=True)
