@@ -13,12 +13,15 @@ namespace {
 constexpr int kChunk = 2048;  // points per reduction chunk
 
 // partial[k][chunk][col], col = blk * B + s.  One work-group per (chunk,
-// block); lanes: state s, rows r striding over the chunk's points.
+// block); lanes: state s, rows r striding over the chunk's points.  With a
+// block map, grid row y covers block bmap[y] (the other blocks' partial
+// sums are left as they are).
 template <int K, typename Op>
 __global__ void __launch_bounds__(256)
-colreduce_kernel(Op op, int64_t np, int B, int nchunks, int N, double *__restrict__ partial) {
+colreduce_kernel(Op op, int64_t np, int B, int nchunks, int N, double *__restrict__ partial,
+                 const int *__restrict__ bmap) {
     __shared__ double red[K][256];
-    const int blk = blockIdx.y, tid = threadIdx.x;
+    const int blk = bmap ? bmap[blockIdx.y] : (int)blockIdx.y, tid = threadIdx.x;
     const int s = tid % B, r = tid / B, R = 256 / B;
     const int64_t p0 = (int64_t)blockIdx.x * kChunk, p1 = min<int64_t>(np, p0 + kChunk);
     const int col = blk * B + s;
@@ -56,13 +59,16 @@ colreduce_final(const double *__restrict__ partial, int K, int nchunks, int N, d
     if (lane == 0) out[idx] = dv * s;
 }
 
+// Sums for all nblk * B columns; with bmap (device, nmap entries) only the
+// listed blocks are reduced this time and the other columns' outputs repeat
+// whatever their partial sums last held.
 template <int K, typename Op>
 rs_status colreduce(const Op &op, int64_t np, int B, int nblk, double dv, double *partial, double *out,
-                    hipStream_t st) {
+                    hipStream_t st, const int *bmap = nullptr, int nmap = 0) {
     const int N = nblk * B;
     const int nchunks = (int)((np + kChunk - 1) / kChunk);
-    hipLaunchKernelGGL((colreduce_kernel<K, Op>), dim3(nchunks, nblk), dim3(256), 0, st, op, np, B, nchunks, N,
-                       partial);
+    hipLaunchKernelGGL((colreduce_kernel<K, Op>), dim3(nchunks, bmap ? nmap : nblk), dim3(256), 0, st, op, np, B,
+                       nchunks, N, partial, bmap);
     RS_HIP(hipGetLastError());
     hipLaunchKernelGGL(colreduce_final, dim3((K * N + 3) / 4), dim3(256), 0, st, partial, K, nchunks, N, dv,
                        out);

@@ -181,12 +181,13 @@ template <typename T, int NIT> struct OpDiis {
 template <typename T>
 __global__ void __launch_bounds__(256)
 axpy1_kernel(const T *__restrict__ x, const T *__restrict__ d, T *y, const double *__restrict__ lam, int64_t np,
-             int B) {
-    // blockIdx.y: the block; B is a power of two
+             int B, const int *__restrict__ bmap) {
+    // blockIdx.y: the block (or its entry in the block map); B is a power of two
+    const int blk = bmap ? bmap[blockIdx.y] : (int)blockIdx.y;
     const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (il >= np * B) return;
-    const int64_t i = (int64_t)blockIdx.y * np * B + il;
-    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
+    const int64_t i = (int64_t)blk * np * B + il;
+    const int c = blk * B + (int)(il & (B - 1));
     y[i] = (T)((double)x[i] + lam[c] * (double)d[i]);
 }
 
@@ -199,14 +200,15 @@ template <typename T> struct Hist {
 template <typename T, int NIT>
 __global__ void __launch_bounds__(256)
 combine_kernel(Hist<T> H, const double *__restrict__ eps, const double *__restrict__ coef, T *__restrict__ xb,
-               T *__restrict__ hb, T *__restrict__ rb, int64_t np, int B, int N) {
+               T *__restrict__ hb, T *__restrict__ rb, int64_t np, int B, int N, const int *__restrict__ bmap) {
     const T *const *xs = H.x;
     const T *const *hs = H.h;
-    // blockIdx.y: the block; B is a power of two
+    // blockIdx.y: the block (or its entry in the block map); B is a power of two
+    const int blk = bmap ? bmap[blockIdx.y] : (int)blockIdx.y;
     const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (il >= np * B) return;
-    const int64_t i = (int64_t)blockIdx.y * np * B + il;
-    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
+    const int64_t i = (int64_t)blk * np * B + il;
+    const int c = blk * B + (int)(il & (B - 1));
     const double xl = xs[NIT - 1][i], hl = hs[NIT - 1][i];
     const double rl = hl - eps[(NIT - 1) * N + c] * xl;
     double sx = coef[c * kMaxHist] * xl, sh = coef[c * kMaxHist] * hl, sr = coef[c * kMaxHist] * rl;
@@ -347,8 +349,11 @@ __global__ void eps1_kernel(const double *__restrict__ d2, const double *__restr
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
     const double l = lam[c];
-    const double num = d2[1 * N + c] + l * (d5[0 * N + c] + d5[1 * N + c]) + l * l * d5[2 * N + c];
-    const double den = d2[0 * N + c] + 2.0 * l * d5[3 * N + c] + l * l * d5[4 * N + c];
+    // lambda 0 (frozen states, whose trial-step dots are not formed): iterate
+    // 1 is iterate 0
+    const double num = l == 0.0 ? d2[1 * N + c]
+                                : d2[1 * N + c] + l * (d5[0 * N + c] + d5[1 * N + c]) + l * l * d5[2 * N + c];
+    const double den = l == 0.0 ? d2[0 * N + c] : d2[0 * N + c] + 2.0 * l * d5[3 * N + c] + l * l * d5[4 * N + c];
     eps1[c] = den > 0.0 ? num / den : 0.0;
 }
 
@@ -404,12 +409,13 @@ __global__ void mix_kernel(const double *__restrict__ d2, const double *__restri
 template <typename T>
 __global__ void __launch_bounds__(256)
 mixdir_kernel(T *__restrict__ d, const T *__restrict__ e, T *__restrict__ hd, const T *__restrict__ he,
-              const double *__restrict__ mix, int64_t np, int B, int N) {
-    // blockIdx.y: the block; B is a power of two
+              const double *__restrict__ mix, int64_t np, int B, int N, const int *__restrict__ bmap) {
+    // blockIdx.y: the block (or its entry in the block map); B is a power of two
+    const int blk = bmap ? bmap[blockIdx.y] : (int)blockIdx.y;
     const int64_t il = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (il >= np * B) return;
-    const int64_t i = (int64_t)blockIdx.y * np * B + il;
-    const int c = (int)blockIdx.y * B + (int)(il & (B - 1));
+    const int64_t i = (int64_t)blk * np * B + il;
+    const int c = blk * B + (int)(il & (B - 1));
     const double b = mix[N + c];
     if (b == 0.0) return;
     const double a = mix[c];
@@ -489,6 +495,8 @@ struct rs_solver {
     rs::DevBuf sigma, R0;        // shifts, recorded residuals
     rs::DevBuf dn, hdn;          // network direction and H applied (with a network)
     rs::DevBuf d13, mix;         // trial-subspace dots; filter / network coefficients
+    rs::DevBuf bmap;             // int [nblk]: blocks of the trial step and DIIS when some are frozen
+    std::vector<int> host_act, host_map;
     rs_cnn *cnn = nullptr;
     int rr_sweeps = kMaxSweeps;
     int steps = 0;
@@ -558,6 +566,11 @@ extern "C" rs_status rs_eigensolve_create(const rs_grid *g, const rs_nl *nl, con
     if (!st) st = s->sigma.alloc(sizeof(double) * N);
     if (!st) st = s->d13.alloc(sizeof(double) * 13 * N);
     if (!st) st = s->mix.alloc(sizeof(double) * 2 * N);
+    if (!st) st = s->bmap.alloc(sizeof(int) * s->nblk);
+    // reductions over a subset of the blocks leave the other columns'
+    // partial sums as they were: start them at zero
+    if (!st && hipMemset(s->partial.p, 0, sizeof(double) * 13 * (size_t)nchunks * N) != hipSuccess)
+        st = fail(RS_EHIP, "rs_eigensolve_create: clearing the reduction scratch failed");
     if (!st && o.record) st = s->R0.alloc(s->field_bytes);
     if (st) {
         rs_ctx_destroy(s->ctx);
@@ -578,17 +591,48 @@ namespace {
 
 // d = K r for the DIIS iterations: the filter, or per state a K_f r + b K_n r
 // with the trial step's coefficients (the network output goes to S->dn).
+// The blocks a step's trial and DIIS passes run on: all of them, or, when
+// the block stopping rule froze some, the others (map: their indices on the
+// device, runs: contiguous ranges for the stencil and network calls, which
+// take a first block and a count).
+struct Blocks {
+    const int *map = nullptr;
+    int n = 0;
+    std::vector<std::pair<int, int>> runs;
+};
+
+// d = K r on the listed blocks: the filter, and with a network its direction
+// mixed in per state
 template <typename T>
-rs_status precond(rs_solver *S, const T *r, T *d, hipStream_t st) {
+rs_status precond(rs_solver *S, const T *r, T *d, const Blocks &bs, hipStream_t st) {
     using namespace rs;
     const rs_grid *g = S->g;
-    rs_status e = filter_apply(g, S->opts.alpha, r, d, S->nblk, S->B, S->dtype, st);
-    if (e || !S->cnn) return e;
-    if ((e = cnn_precondition(S->cnn, g, r, S->sigma.as<double>(), S->dn.p, S->nblk, S->B, S->dtype, st))) return e;
-    const dim3 gb((unsigned)((g->np * S->B + 255) / 256), S->nblk);
+    const int64_t bel = g->np * S->B;
+    for (const auto &run : bs.runs) {
+        const int64_t off = run.first * bel;
+        rs_status e = filter_apply(g, S->opts.alpha, r + off, d + off, run.second, S->B, S->dtype, st);
+        if (e) return e;
+        if (S->cnn && (e = cnn_precondition(S->cnn, g, r + off, S->sigma.as<double>() + run.first * S->B,
+                                            S->dn.as<T>() + off, run.second, S->B, S->dtype, st)))
+            return e;
+    }
+    if (!S->cnn) return RS_OK;
+    const dim3 gb((unsigned)((g->np * S->B + 255) / 256), bs.n);
     hipLaunchKernelGGL(mixdir_kernel<T>, gb, dim3(256), 0, st, d, S->dn.as<T>(), (T *)nullptr, (const T *)nullptr,
-                       S->mix.as<double>(), g->np, S->B, S->N);
+                       S->mix.as<double>(), g->np, S->B, S->N, bs.map);
     RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+// H applied to the listed blocks of x
+template <typename T>
+rs_status hpsi_blocks(rs_solver *S, const T *x, T *hx, const Blocks &bs, hipStream_t st) {
+    const int64_t bel = S->g->np * S->B;
+    for (const auto &run : bs.runs) {
+        const int64_t off = run.first * bel;
+        rs_status e = rs::hpsi_apply(S->g, S->nl, S->vloc, x + off, hx + off, run.second, S->B, S->dtype, st);
+        if (e) return e;
+    }
     return RS_OK;
 }
 
@@ -599,7 +643,6 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     const int64_t np = g->np;
     const int B = S->B, nblk = S->nblk, N = S->N, m = S->opts.m;
     const double dv = g->h * g->h * g->h;
-    const dim3 gb((unsigned)((np * B + 255) / 256), nblk);   // per-block grid (y: the block)
     const unsigned gs = (unsigned)((N + 63) / 64);
     T *h0 = S->hh[0].as<T>();
     double *partial = S->partial.as<double>();
@@ -625,28 +668,69 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     hipLaunchKernelGGL(active_kernel, dim3(gs), dim3(64), 0, st, S->rr.as<double>(), N, B, S->opts.tol,
                        S->opts.block_stop, S->res.as<double>(), S->active.as<int>());
     if (S->opts.record) RS_HIP(hipMemcpyAsync(S->R0.p, S->R.p, S->field_bytes, hipMemcpyDeviceToDevice, st));
+    // Block stopping rule (Sec. 9): the trial step and the DIIS iterations
+    // run only on blocks with a state above tolerance; frozen blocks keep
+    // psi.  Reading the flags costs one wait on the stream per step, taken
+    // only when a block can freeze (block_stop and tol > 0).
+    Blocks bs;
+    bs.n = nblk;
+    bs.runs.assign(1, {0, nblk});
+    if (S->opts.block_stop && S->opts.tol > 0.0) {
+        S->host_act.resize(N);
+        RS_HIP(hipMemcpyAsync(S->host_act.data(), S->active.p, sizeof(int) * N, hipMemcpyDeviceToHost, st));
+        RS_HIP(hipStreamSynchronize(st));
+        S->host_map.clear();
+        for (int b = 0; b < nblk; ++b)
+            if (S->host_act[(size_t)b * B]) S->host_map.push_back(b);
+        if (S->host_map.empty()) {
+            // every block frozen: psi stays; no state mixed a network direction
+            if (S->cnn) RS_HIP(hipMemsetAsync(S->mix.p, 0, sizeof(double) * 2 * N, st));
+            return RS_OK;
+        }
+        if ((int)S->host_map.size() < nblk) {
+            RS_HIP(hipMemcpyAsync(S->bmap.p, S->host_map.data(), sizeof(int) * S->host_map.size(),
+                                  hipMemcpyHostToDevice, st));
+            bs.map = S->bmap.as<int>();
+            bs.n = (int)S->host_map.size();
+            bs.runs.clear();
+            for (int i = 0; i < bs.n; ++i) {
+                if (i > 0 && S->host_map[i] == S->host_map[i - 1] + 1) ++bs.runs.back().second;
+                else bs.runs.push_back({S->host_map[i], 1});
+            }
+        }
+    }
+    const dim3 ga((unsigned)((np * B + 255) / 256), bs.n);   // grid over the active blocks (y: map entry)
     // 3. trial step
-    if ((e = filter_apply(g, S->opts.alpha, S->R.p, S->d.p, nblk, B, S->dtype, st))) return e;
-    if ((e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
+    for (const auto &run : bs.runs) {
+        const int64_t off = run.first * np * B;
+        if ((e = filter_apply(g, S->opts.alpha, S->R.as<T>() + off, S->d.as<T>() + off, run.second, B, S->dtype,
+                              st)))
+            return e;
+    }
+    if ((e = hpsi_blocks<T>(S, S->d.as<T>(), S->hd.as<T>(), bs, st))) return e;
     if (!S->cnn) {
         if ((e = colreduce<5>(OpLam<T>{psi, h0, S->d.as<T>(), S->hd.as<T>()}, np, B, nblk, dv, partial,
-                              S->d5.as<double>(), st)))
+                              S->d5.as<double>(), st, bs.map, bs.n)))
             return e;
         hipLaunchKernelGGL(lambda_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d5.as<double>(),
                            S->active.as<int>(), N, S->lam.as<double>());
     } else {
         // the network's direction and the 3x3 trial problem; the mixed
         // direction replaces d (and H d) for the states that use it
-        if ((e = cnn_precondition(S->cnn, g, S->R.p, S->sigma.as<double>(), S->dn.p, nblk, B, S->dtype, st)))
-            return e;
-        if ((e = hpsi_apply(g, S->nl, S->vloc, S->dn.p, S->hdn.p, nblk, B, S->dtype, st))) return e;
+        for (const auto &run : bs.runs) {
+            const int64_t off = run.first * np * B;
+            if ((e = cnn_precondition(S->cnn, g, S->R.as<T>() + off, S->sigma.as<double>() + run.first * B,
+                                      S->dn.as<T>() + off, run.second, B, S->dtype, st)))
+                return e;
+        }
+        if ((e = hpsi_blocks<T>(S, S->dn.as<T>(), S->hdn.as<T>(), bs, st))) return e;
         if ((e = colreduce<13>(OpLam3<T>{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->dn.as<T>(), S->hdn.as<T>()}, np,
-                               B, nblk, dv, partial, S->d13.as<double>(), st)))
+                               B, nblk, dv, partial, S->d13.as<double>(), st, bs.map, bs.n)))
             return e;
         hipLaunchKernelGGL(mix_kernel, dim3(gs), dim3(64), 0, st, S->d2.as<double>(), S->d13.as<double>(),
                            S->active.as<int>(), N, S->lam.as<double>(), S->mix.as<double>());
-        hipLaunchKernelGGL(mixdir_kernel<T>, gb, dim3(256), 0, st, S->d.as<T>(), S->dn.as<T>(), S->hd.as<T>(),
-                           S->hdn.as<T>(), S->mix.as<double>(), np, B, N);
+        hipLaunchKernelGGL(mixdir_kernel<T>, ga, dim3(256), 0, st, S->d.as<T>(), S->dn.as<T>(), S->hd.as<T>(),
+                           S->hdn.as<T>(), S->mix.as<double>(), np, B, N, bs.map);
         RS_HIP(hipGetLastError());
     }
     // history: iterate 0 is psi itself
@@ -655,8 +739,8 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
     hs[0] = h0;
     if (m == 1) {
         // the trial iterate is the newest: straight into psi (in place)
-        hipLaunchKernelGGL(axpy1_kernel<T>, gb, dim3(256), 0, st, psi, S->d.as<T>(), psi,
-                           S->lam.as<double>(), np, B);
+        hipLaunchKernelGGL(axpy1_kernel<T>, ga, dim3(256), 0, st, psi, S->d.as<T>(), psi,
+                           S->lam.as<double>(), np, B, bs.map);
         RS_HIP(hipGetLastError());
         return RS_OK;
     }
@@ -669,7 +753,7 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
                            S->lam.as<double>(), N, S->eps.as<double>() + N);
     } else if ((e = colreduce<2>(OpAxpy2Dots<T>{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->hx[1].as<T>(),
                                                S->hh[1].as<T>(), S->lam.as<double>()},
-                                 np, B, nblk, dv, partial, S->d2.as<double>(), st))) {
+                                 np, B, nblk, dv, partial, S->d2.as<double>(), st, bs.map, bs.n))) {
         return e;
     }
     xs[1] = S->hx[1].as<T>();
@@ -683,13 +767,14 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
         if (n == 2 && fused1) {
             OpDiis2New<T> op{psi, h0, S->d.as<T>(), S->hd.as<T>(), S->hx[1].as<T>(), S->hh[1].as<T>(),
                              S->lam.as<double>(), S->eps.as<double>(), N};
-            if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
+            if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st, bs.map, bs.n))) return e;
         } else if (n == 2) {
             OpDiis<T, 2> op{{xs[0], xs[1]}, {hs[0], hs[1]}, S->eps.as<double>(), N};
-            if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
+            if ((e = colreduce<6>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st, bs.map, bs.n))) return e;
         } else {
             OpDiis<T, 3> op{{xs[0], xs[1], xs[2]}, {hs[0], hs[1], hs[2]}, S->eps.as<double>(), N};
-            if ((e = colreduce<12>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st))) return e;
+            if ((e = colreduce<12>(op, np, B, nblk, dv, partial, S->mats.as<double>(), st, bs.map, bs.n)))
+                return e;
         }
         hipLaunchKernelGGL(diis_kernel, dim3(gs), dim3(64), 0, st, S->mats.as<double>(), n, S->lam.as<double>(), N,
                            S->coef.as<double>());
@@ -702,25 +787,25 @@ rs_status step_impl(rs_solver *S, T *psi, hipStream_t st) {
             hist.h[i] = hs[i];
         }
         if (n == 2)
-            hipLaunchKernelGGL((combine_kernel<T, 2>), gb, dim3(256), 0, st, hist, S->eps.as<double>(),
-                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N);
+            hipLaunchKernelGGL((combine_kernel<T, 2>), ga, dim3(256), 0, st, hist, S->eps.as<double>(),
+                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, bs.map);
         else
-            hipLaunchKernelGGL((combine_kernel<T, 3>), gb, dim3(256), 0, st, hist, S->eps.as<double>(),
-                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N);
+            hipLaunchKernelGGL((combine_kernel<T, 3>), ga, dim3(256), 0, st, hist, S->eps.as<double>(),
+                               S->coef.as<double>(), xb, hb, S->R.as<T>(), np, B, N, bs.map);
         RS_HIP(hipGetLastError());
-        if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), st))) return e;
+        if ((e = precond<T>(S, S->R.as<T>(), S->d.as<T>(), bs, st))) return e;
         // H d only where another DIIS iteration follows: the last update
         // needs d alone
-        if (n < m && (e = hpsi_apply(g, S->nl, S->vloc, S->d.p, S->hd.p, nblk, B, S->dtype, st))) return e;
+        if (n < m && (e = hpsi_blocks<T>(S, S->d.as<T>(), S->hd.as<T>(), bs, st))) return e;
         if (n < m) {
             if ((e = colreduce<2>(OpAxpy2Dots<T>{xb, hb, S->d.as<T>(), S->hd.as<T>(), xb, hb, S->lam.as<double>()},
-                                  np, B, nblk, dv, partial, S->d2.as<double>(), st)))
+                                  np, B, nblk, dv, partial, S->d2.as<double>(), st, bs.map, bs.n)))
                 return e;
         } else {
-            // the newest iterate goes straight into psi (frozen states: it
-            // equals psi); its H psi is not needed
-            hipLaunchKernelGGL(axpy1_kernel<T>, gb, dim3(256), 0, st, xb, S->d.as<T>(), psi,
-                               S->lam.as<double>(), np, B);
+            // the newest iterate goes straight into psi; its H psi is not
+            // needed
+            hipLaunchKernelGGL(axpy1_kernel<T>, ga, dim3(256), 0, st, xb, S->d.as<T>(), psi,
+                               S->lam.as<double>(), np, B, bs.map);
         }
         xs[n] = xb;
         hs[n] = hb;

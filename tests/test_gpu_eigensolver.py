@@ -64,6 +64,34 @@ def test_block_stop_freezes_converged_blocks():
     assert np.max(np.abs(got - p2)) < 1e-9 * np.max(np.abs(p2))
 
 
+@pytest.mark.parametrize("m", [1, 3])
+def test_step_with_a_frozen_block_matches_oracle(m):
+    """Block stopping rule (Sec. 9) with the lower block frozen and the upper
+    one active: the GPU runs the trial step and the DIIS iterations on the
+    active block only, the frozen states keep psi up to the final
+    orthonormalisation, and the step agrees with the oracle's."""
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2)
+    N, B = 16, 8
+    og, H, g, _, psi = _setup(w, N, B, m=m, tol=1e-12)
+    opts0 = rmmdiis.Options(m=m, block=B, tol=1e-12)
+    for _ in range(6):
+        psi = rmmdiis.rmmdiis_step(H, psi, opts0)["psi"]
+    # a tolerance just above the lower block's residuals of the next step
+    r = rmmdiis.rmmdiis_step(H, psi, opts0)["resnorm"]
+    tol = float(np.max(r[:B])) * (1.0 + 1e-6)
+    assert np.max(r[B:]) > 1.01 * tol
+    want = rmmdiis.rmmdiis_step(H, psi, rmmdiis.Options(m=m, block=B, tol=tol))
+    assert not want["active"][:B].any() and want["active"][B:].all()
+    _, _, _, solver, _ = _setup(w, N, B, m=m, tol=tol)
+    t = torch.from_numpy(rsd.to_blocks(psi, B)).to(DEV)
+    eig, res, nconv = solver.step(t)
+    assert solver.stats()["frozen_blocks"] == 1
+    got = rsd.from_blocks(t.cpu().numpy())
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) < 1e-10 * np.max(np.abs(want["psi"]))
+
+
 def test_converges_harmonic_box():
     """Lowest four levels of the 32^3 harmonic box from random states."""
     w = synthetic.make_workload("box32_harmonic", nstates=4)
