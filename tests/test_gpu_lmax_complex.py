@@ -63,8 +63,9 @@ def _hpsi(g, nl, v, psi_sm, B, dtype, vdtype):
 @pytest.mark.parametrize("lmax", [0, 2, 3])
 @pytest.mark.parametrize("B", [8, 32])
 def test_hpsi_fp64_lmax(lmax, B):
-    """B = 32 runs the z-marching kernel plus the point-centric projector
-    add, B = 8 the per-brick kernel with the projector term fused."""
+    """B = 32 runs the z-marching kernel, B = 8 the per-brick kernel; both
+    then the point-centric projector add (the per-brick kernel fuses the
+    projector term only for the 4-projector s and p set)."""
     og, H, g, nl = _system(SMALL, lmax)
     psi = _states(SMALL, 2 * B, og.np)
     got = _hpsi(g, nl, H.vloc, psi, B, np.float64, np.float64)
@@ -197,3 +198,29 @@ def test_complex_block_limits_at_the_c_abi():
                       ctypes.c_void_p(S.data_ptr()), 1, 16, _abi.RS_C128, _abi.RS_PREC_NATIVE, None)
     assert rc == _abi.RS_EINVAL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+def test_full_size_sphere_lmax3_sampled(dtype, tol):
+    """The 904k-point sphere with 16 atoms carrying 16 projectors each (l <= 3),
+    all 128 states in blocks of 32 (FP64: z-marching kernel and projector
+    add; FP32: per-brick kernel and projector add), checked at sampled points
+    computed one by one by the oracle."""
+    from oracle import stencil
+    w = synthetic.WORKLOADS["sphere_r12_h0.2"]
+    og, atoms, H0 = hamiltonian.build_system(w, with_projectors=False)
+    D = synthetic.couplings_lmax(w, atoms, 3)
+    ps = kb.build_projectors(og, atoms.pos, D, w.rc, w.sigma, lmax=3)
+    g = rsd.Grid.for_workload(w)
+    nl = rsd.NonLocal(g, atoms.pos, D, w.rc, w.sigma, max_states=128, lmax=3)
+    psi = _states(w, 128, og.np).astype(dtype)
+    v = H0.vloc.astype(dtype)
+    got = _hpsi(g, nl, v, psi, 32, dtype, dtype)
+    x64 = psi.astype(np.float64)
+    rng = np.random.default_rng(13)
+    pts = rng.choice(og.np, 300, replace=False)
+    sph = np.concatenate(ps.idx)
+    pts = np.unique(np.concatenate([pts, rng.choice(sph, 200, replace=False)]))
+    want = stencil.apply_local_at(og, v.astype(np.float64), x64, pts)
+    want += kb.apply_projections(ps, kb.project(ps, x64), og.np)[:, pts]
+    assert _relerr(got[:, pts], want) < tol
