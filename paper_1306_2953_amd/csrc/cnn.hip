@@ -44,73 +44,132 @@ __device__ __forceinline__ int wrap_or_flag(int v, int n, bool wrap, bool &ok) {
 // ------------------------------------------------------------ convolution
 // MODE 0: out = mask * tanh(conv(in));  MODE 1: out = mask * conv(in);
 // MODE 2: out = mask * conv(in) * (1 - act^2)  (backward through tanh).
-// W [CO][CI][27].  Thread per output point; the weights are wave-uniform.
+// W [CO][CI][27]; taps outside the box are zero (or wrap).  A work-group
+// owns a TZ x TY x TX block of outputs of one box: it stages the block and
+// its one-point border, channels last, in LDS once, then each thread
+// computes two x-neighbouring outputs from there, which share the loads of
+// their taps.  Per output the sum runs over taps t = 9 dz + 3 dy + dx, then
+// output channel, then input channel, one fused multiply-add each; the
+// weights are uniform across the work-group.
+constexpr int kTX = 16, kTY = 8, kTZ = 4;   // 512 outputs per work-group, 2 per thread
+
 template <int CI, int CO, int MODE>
 __global__ void __launch_bounds__(256)
 conv_kernel(const float *__restrict__ in, float *__restrict__ out, const float *__restrict__ W,
             const float *__restrict__ act, const int32_t *__restrict__ boxpt, int n, int Z, int Y, int X,
-            int wrap) {
+            int wrap, int ntx, int nty, int ntz) {
+    constexpr int HX = kTX + 2, HY = kTY + 2, HZ = kTZ + 2;
+    __shared__ __attribute__((aligned(16))) float tile[HZ * HY * HX * CI];
+    const int bid = blockIdx.x;
+    const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = (bid / (ntx * nty)) % ntz;
+    const int img = bid / (ntx * nty * ntz);
+    const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
     const int vol = Z * Y * X;
-    const int gid = blockIdx.x * 256 + threadIdx.x;
-    if (gid >= vol * n) return;
-    const int img = gid / vol, q = gid - img * vol;
-    const int x = q % X, y = (q / X) % Y, z = q / (X * Y);
     const float *base = in + (int64_t)img * vol * CI;
-    float acc[CO];
-#pragma unroll
-    for (int c = 0; c < CO; ++c) acc[c] = 0.f;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
-        bool okz = true;
-        const int zz = wrap_or_flag(z + dz - 1, Z, wrap, okz);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            bool oky = okz;
-            const int yy = wrap_or_flag(y + dy - 1, Y, wrap, oky);
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                bool ok = oky;
-                const int xx = wrap_or_flag(x + dx - 1, X, wrap, ok);
-                if (!ok) continue;
-                const int t = 9 * dz + 3 * dy + dx;
+    // stage the block and its border; positions more than one point past the
+    // box feed only outputs that are not computed and are left zero
+    for (int e = threadIdx.x; e < HZ * HY * HX; e += 256) {
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        bool ok = gx <= X && gy <= Y && gz <= Z;
+        const int xx = wrap_or_flag(gx, X, wrap, ok);
+        const int yy = wrap_or_flag(gy, Y, wrap, ok);
+        const int zz = wrap_or_flag(gz, Z, wrap, ok);
+        ok = ok && xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z;
+        float *dst = tile + e * CI;
+        if constexpr (CI == 8) {
+            float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+            if (ok) {
                 const float *src = base + ((int64_t)(zz * Y + yy) * X + xx) * CI;
-                float v[CI];
+                lo = *(const float4 *)src;
+                hi = *(const float4 *)(src + 4);
+            }
+            *(float4 *)dst = lo;
+            *(float4 *)(dst + 4) = hi;
+        } else {
+#pragma unroll
+            for (int c = 0; c < CI; ++c) dst[c] = ok ? base[((int64_t)(zz * Y + yy) * X + xx) * CI + c] : 0.f;
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int lx = 2 * (t % (kTX / 2)), ly = (t / (kTX / 2)) % kTY, lz = t / (kTX / 2 * kTY);
+    float acc0[CO], acc1[CO];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) acc0[c] = acc1[c] = 0.f;
+    // (dz, dy) stays a loop: unrolled, the loads of all nine rows would be
+    // hoisted and the work-group would run at one wave per SIMD
+#pragma unroll 1
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll 1
+        for (int dy = 0; dy < 3; ++dy) {
+            // border coordinates: output lx sits at lx + 1, tap dx reads lx + dx
+            const float *row = tile + (((lz + dz) * HY + (ly + dy)) * HX + lx) * CI;
+            float v[4][CI];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
                 if constexpr (CI == 8) {
-                    const float4 lo = *(const float4 *)src, hi = *(const float4 *)(src + 4);
-                    v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
-                    v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+                    const float4 lo = *(const float4 *)(row + j * CI), hi = *(const float4 *)(row + j * CI + 4);
+                    v[j][0] = lo.x; v[j][1] = lo.y; v[j][2] = lo.z; v[j][3] = lo.w;
+                    v[j][4] = hi.x; v[j][5] = hi.y; v[j][6] = hi.z; v[j][7] = hi.w;
                 } else {
 #pragma unroll
-                    for (int c = 0; c < CI; ++c) v[c] = src[c];
+                    for (int c = 0; c < CI; ++c) v[j][c] = row[j * CI + c];
                 }
+            }
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int tap = 9 * dz + 3 * dy + dx;
 #pragma unroll
                 for (int co = 0; co < CO; ++co)
 #pragma unroll
-                    for (int ci = 0; ci < CI; ++ci) acc[co] = fmaf(W[(co * CI + ci) * 27 + t], v[ci], acc[co]);
+                    for (int ci = 0; ci < CI; ++ci) {
+                        const float w = W[(co * CI + ci) * 27 + tap];
+                        acc0[co] = fmaf(w, v[dx][ci], acc0[co]);
+                        acc1[co] = fmaf(w, v[dx + 1][ci], acc1[co]);
+                    }
             }
         }
-    }
-    const bool inside = boxpt == nullptr || boxpt[q] >= 0;
-    float *dst = out + (int64_t)gid * CO;
-    float r[CO];
+    const int y = y0 + ly, z = z0 + lz;
 #pragma unroll
-    for (int c = 0; c < CO; ++c) {
-        float o;
-        if constexpr (MODE == 0) o = tanhf(acc[c]);
-        else if constexpr (MODE == 1) o = acc[c];
-        else {
-            const float a = act[(int64_t)gid * CO + c];
-            o = acc[c] * (1.f - a * a);
+    for (int k = 0; k < 2; ++k) {
+        const int x = x0 + lx + k;
+        if (x >= X || y >= Y || z >= Z) continue;
+        const int q = (z * Y + y) * X + x;
+        const int64_t gid = (int64_t)img * vol + q;
+        const bool inside = boxpt == nullptr || boxpt[q] >= 0;
+        float *dst = out + gid * CO;
+        float r[CO];
+#pragma unroll
+        for (int c = 0; c < CO; ++c) {
+            const float a = k == 0 ? acc0[c] : acc1[c];
+            float o;
+            if constexpr (MODE == 0) o = tanhf(a);
+            else if constexpr (MODE == 1) o = a;
+            else {
+                const float ac = act[gid * CO + c];
+                o = a * (1.f - ac * ac);
+            }
+            r[c] = inside ? o : 0.f;
         }
-        r[c] = inside ? o : 0.f;
-    }
-    if constexpr (CO == 8) {
-        *(float4 *)dst = make_float4(r[0], r[1], r[2], r[3]);
-        *(float4 *)(dst + 4) = make_float4(r[4], r[5], r[6], r[7]);
-    } else {
+        if constexpr (CO == 8) {
+            *(float4 *)dst = make_float4(r[0], r[1], r[2], r[3]);
+            *(float4 *)(dst + 4) = make_float4(r[4], r[5], r[6], r[7]);
+        } else {
 #pragma unroll
-        for (int c = 0; c < CO; ++c) dst[c] = r[c];
+            for (int c = 0; c < CO; ++c) dst[c] = r[c];
+        }
     }
+}
+
+// Launches conv_kernel over n boxes of Z x Y x X points.
+template <int CI, int CO, int MODE>
+void conv(const float *in, float *out, const float *W, const float *act, const int32_t *boxpt, int n, int Z, int Y,
+          int X, int wrap, hipStream_t st) {
+    const int ntx = (X + kTX - 1) / kTX, nty = (Y + kTY - 1) / kTY, ntz = (Z + kTZ - 1) / kTZ;
+    const int64_t nwg = (int64_t)ntx * nty * ntz * n;
+    hipLaunchKernelGGL((conv_kernel<CI, CO, MODE>), dim3((unsigned)nwg), dim3(256), 0, st, in, out, W, act, boxpt, n,
+                       Z, Y, X, wrap, ntx, nty, ntz);
 }
 
 // Weights of the input adjoint: Wt[ci][co][26 - t] = W[co][ci][t].
@@ -548,15 +607,10 @@ rs_status ensure(rs::DevBuf &b, size_t bytes) { return b.bytes >= bytes ? RS_OK 
 // f = network(u) for n boxes; activations kept in a1, a2.
 rs_status forward(rs_cnn *c, const float *u, float *f, int n, int Z, int Y, int X, int wrap,
                   const int32_t *boxpt, hipStream_t st) {
-    const int64_t tot = (int64_t)n * Z * Y * X;
-    const unsigned gsz = (unsigned)((tot + 255) / 256);
     const float *P = c->params.as<float>();
-    hipLaunchKernelGGL((conv_kernel<1, 8, 0>), dim3(gsz), dim3(256), 0, st, u, c->a1.as<float>(), P + kW1, nullptr,
-                       boxpt, n, Z, Y, X, wrap);
-    hipLaunchKernelGGL((conv_kernel<8, 8, 0>), dim3(gsz), dim3(256), 0, st, c->a1.as<float>(), c->a2.as<float>(),
-                       P + kW2, nullptr, boxpt, n, Z, Y, X, wrap);
-    hipLaunchKernelGGL((conv_kernel<8, 1, 1>), dim3(gsz), dim3(256), 0, st, c->a2.as<float>(), f, P + kW3, nullptr,
-                       boxpt, n, Z, Y, X, wrap);
+    conv<1, 8, 0>(u, c->a1.as<float>(), P + kW1, nullptr, boxpt, n, Z, Y, X, wrap, st);
+    conv<8, 8, 0>(c->a1.as<float>(), c->a2.as<float>(), P + kW2, nullptr, boxpt, n, Z, Y, X, wrap, st);
+    conv<8, 1, 1>(c->a2.as<float>(), f, P + kW3, nullptr, boxpt, n, Z, Y, X, wrap, st);
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -720,19 +774,16 @@ extern "C" rs_status rs_cnn_loss_grad(rs_cnn *c, const float *u, const float *t,
     // layer 3: weights, then delta of layer 2 (through tanh)
     hipLaunchKernelGGL((wgrad_kernel<8, 1>), dim3(nwg), dim3(256), 0, st, a2, df, n, Z, Y, X, 0, c->wpart.as<float>());
     hipLaunchKernelGGL(wgrad_final, dim3((216 + 3) / 4), dim3(256), 0, st, c->wpart.as<float>(), nwg, 216, G + kW3);
-    hipLaunchKernelGGL((conv_kernel<1, 8, 2>), dim3(gsz), dim3(256), 0, st, df, d2, WT + kW3, a2, nullptr, n, Z, Y, X,
-                       0);
+    conv<1, 8, 2>(df, d2, WT + kW3, a2, nullptr, n, Z, Y, X, 0, st);
     // layer 2
     hipLaunchKernelGGL((wgrad_kernel<8, 8>), dim3(nwg), dim3(256), 0, st, a1, d2, n, Z, Y, X, 0, c->wpart.as<float>());
     hipLaunchKernelGGL(wgrad_final, dim3((1728 + 3) / 4), dim3(256), 0, st, c->wpart.as<float>(), nwg, 1728, G + kW2);
-    hipLaunchKernelGGL((conv_kernel<8, 8, 2>), dim3(gsz), dim3(256), 0, st, d2, d1, WT + kW2, a1, nullptr, n, Z, Y, X,
-                       0);
+    conv<8, 8, 2>(d2, d1, WT + kW2, a1, nullptr, n, Z, Y, X, 0, st);
     // layer 1
     hipLaunchKernelGGL((wgrad_kernel<1, 8>), dim3(nwg), dim3(256), 0, st, u, d1, n, Z, Y, X, 0, c->wpart.as<float>());
     hipLaunchKernelGGL(wgrad_final, dim3((216 + 3) / 4), dim3(256), 0, st, c->wpart.as<float>(), nwg, 216, G + kW1);
     if (du)
-        hipLaunchKernelGGL((conv_kernel<8, 1, 1>), dim3(gsz), dim3(256), 0, st, d1, du, WT + kW1, nullptr, nullptr, n,
-                           Z, Y, X, 0);
+        conv<8, 1, 1>(d1, du, WT + kW1, nullptr, nullptr, n, Z, Y, X, 0, st);
     RS_HIP(hipGetLastError());
     if (loss) RS_HIP(hipMemcpyAsync(loss, c->loss.p, sizeof(double), hipMemcpyDeviceToHost, st));
     if (grad) RS_HIP(hipMemcpyAsync(grad, G, kNP * sizeof(float), hipMemcpyDeviceToHost, st));
