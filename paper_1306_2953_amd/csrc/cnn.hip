@@ -172,6 +172,129 @@ void conv(const float *in, float *out, const float *W, const float *act, const i
                        Z, Y, X, wrap, ntx, nty, ntz);
 }
 
+// Layer 2 of the forward pass (8 -> 8 channels, tanh) on the matrix cores:
+// per row of 16 outputs an implicit GEMM D[point][co] = sum over k = (tap,
+// ci) of A[point][k] W[co][ci][tap], K = 27 taps x 8 channels in 7 chunks of
+// 32 (4 taps each; the 28th tap gets zero weights), N = the 8 channels of a
+// 16-wide tile.  Inputs and weights are split as hi + lo bfloat16 (the
+// input block once per work-group, into hi and lo planes in LDS) and the
+// four products lo.lo + hi.lo + lo.hi + hi.hi are summed in FP32 on
+// mfma_f32_16x16x32_bf16, which keeps FP32 accuracy.  Lane l supplies A row
+// l % 16 (point x0 + l % 16) and B column l % 16 (channel), both for k =
+// 8 (l / 16) .. + 7 (tap 4 c + l / 16 of chunk c, channels 0..7), and
+// receives D rows 4 (l / 16) + r, r < 4, of column l % 16.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// bfloat16 with round-to-nearest-even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+__global__ void __launch_bounds__(256)
+conv2_mfma_kernel(const float *__restrict__ in, float *__restrict__ out, const float *__restrict__ W,
+                  const int32_t *__restrict__ boxpt, int n, int Z, int Y, int X, int wrap, int ntx, int nty,
+                  int ntz) {
+    constexpr int HX = kTX + 2, HY = kTY + 2, HZ = kTZ + 2, NH = HX * HY * HZ;
+    __shared__ __attribute__((aligned(16))) unsigned short th[NH * 8], tl[NH * 8];
+    const int vol = Z * Y * X;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // this lane's B operands (channel co, taps 4 c + g of the 7 chunks) and
+    // the LDS offsets of its A operands relative to the row's first point,
+    // once for all the tiles this work-group takes
+    const int co = lane % 16, g = lane / 16;
+    bf8 bh[7], bl[7];
+    int aoff[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        const int tap = 4 * c + g;
+        us8 h, l;
+#pragma unroll
+        for (int ci = 0; ci < 8; ++ci) {
+            const float w = co < 8 && tap < 27 ? W[(co * 8 + ci) * 27 + tap] : 0.f;
+            h[ci] = bf16_rne(w);
+            l[ci] = bf16_rne(w - bf16_to_f(h[ci]));
+        }
+        bh[c] = __builtin_bit_cast(bf8, h);
+        bl[c] = __builtin_bit_cast(bf8, l);
+        const int t = min(tap, 26);   // the 28th tap: zero weights, any finite input
+        aoff[c] = (((t / 9) * HY + (t / 3) % 3) * HX + t % 3 + co) * 8;
+    }
+    const int ntile = ntx * nty * ntz * n;
+    for (int bid = blockIdx.x; bid < ntile; bid += gridDim.x) {
+        const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = (bid / (ntx * nty)) % ntz;
+        const int img = bid / (ntx * nty * ntz);
+        const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+        const float *base = in + (int64_t)img * vol * 8;
+        __syncthreads();   // the previous tile's reads of the LDS block are done
+        for (int e = tid; e < NH; e += 256) {
+            const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            bool ok = gx <= X && gy <= Y && gz <= Z;
+            const int xx = wrap_or_flag(gx, X, wrap, ok);
+            const int yy = wrap_or_flag(gy, Y, wrap, ok);
+            const int zz = wrap_or_flag(gz, Z, wrap, ok);
+            ok = ok && xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z;
+            float v[8];
+            if (ok) {
+                const float *src = base + ((int64_t)(zz * Y + yy) * X + xx) * 8;
+                const float4 a = *(const float4 *)src, b = *(const float4 *)(src + 4);
+                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v[c] = 0.f;
+            }
+            us8 h, l;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                h[c] = bf16_rne(v[c]);
+                l[c] = bf16_rne(v[c] - bf16_to_f(h[c]));
+            }
+            *(us8 *)(th + e * 8) = h;
+            *(us8 *)(tl + e * 8) = l;
+        }
+        __syncthreads();
+        for (int row = wave; row < kTZ * kTY; row += 4) {
+            const int lz = row / kTY, ly = row % kTY;
+            const int rb = (lz * HY + ly) * HX * 8;
+            // one accumulator per product: four independent chains
+            f4 acc[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                const bf8 ah = __builtin_bit_cast(bf8, *(const us8 *)(th + rb + aoff[c]));
+                const bf8 al = __builtin_bit_cast(bf8, *(const us8 *)(tl + rb + aoff[c]));
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bl[c], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[2], 0, 0, 0);
+                acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[3], 0, 0, 0);
+            }
+            // the small products first; lanes of channels 0..7 hold the 4
+            // outputs of rows 4 g .. 4 g + 3, and hand the last two to the
+            // lane 8 above (whose channel column is empty), so every lane
+            // evaluates two tanh
+            const f4 d = ((acc[0] + acc[1]) + acc[2]) + acc[3];
+            const float s0 = __shfl_xor(d[2], 8, 64), s1 = __shfl_xor(d[3], 8, 64);
+            const int cc = co & 7, r0 = co < 8 ? 0 : 2;
+            const float v0 = co < 8 ? d[0] : s0, v1 = co < 8 ? d[1] : s1;
+            const int y = y0 + ly, z = z0 + lz;
+            if (y >= Y || z >= Z) continue;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int x = x0 + 4 * g + r0 + k;
+                if (x >= X) continue;
+                const int q = (z * Y + y) * X + x;
+                const bool inside = boxpt == nullptr || boxpt[q] >= 0;
+                out[((int64_t)img * vol + q) * 8 + cc] = inside ? tanhf(k == 0 ? v0 : v1) : 0.f;
+            }
+        }
+    }
+}
+
 // Weights of the input adjoint: Wt[ci][co][26 - t] = W[co][ci][t].
 __global__ void flip_kernel(const float *__restrict__ params, float *__restrict__ wt) {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -609,7 +732,13 @@ rs_status forward(rs_cnn *c, const float *u, float *f, int n, int Z, int Y, int 
                   const int32_t *boxpt, hipStream_t st) {
     const float *P = c->params.as<float>();
     conv<1, 8, 0>(u, c->a1.as<float>(), P + kW1, nullptr, boxpt, n, Z, Y, X, wrap, st);
-    conv<8, 8, 0>(c->a1.as<float>(), c->a2.as<float>(), P + kW2, nullptr, boxpt, n, Z, Y, X, wrap, st);
+    {
+        const int ntx = (X + kTX - 1) / kTX, nty = (Y + kTY - 1) / kTY, ntz = (Z + kTZ - 1) / kTZ;
+        // at most three work-groups per CU resident; each takes tiles in turn
+        const int64_t nwg = std::min<int64_t>((int64_t)ntx * nty * ntz * n, 3 * 256);
+        hipLaunchKernelGGL(conv2_mfma_kernel, dim3((unsigned)nwg), dim3(256), 0, st, c->a1.as<float>(),
+                           c->a2.as<float>(), P + kW2, boxpt, n, Z, Y, X, wrap, ntx, nty, ntz);
+    }
     conv<8, 1, 1>(c->a2.as<float>(), f, P + kW3, nullptr, boxpt, n, Z, Y, X, wrap, st);
     RS_HIP(hipGetLastError());
     return RS_OK;
