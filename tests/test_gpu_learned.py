@@ -94,6 +94,44 @@ def test_step_with_network_matches_oracle(kind):
     assert perr < 1e-6
 
 
+def test_step_with_network_and_a_frozen_block_matches_oracle():
+    """The block stopping rule with a network: the lower block frozen, the
+    upper one takes the 3x3 trial step and the mixed direction (the network
+    runs on the active block only)."""
+    from oracle import cnn as ocnn, hamiltonian, linalg, rmmdiis
+    w = synthetic.make_workload("sphere_r12_h0.2", radius=2.4, nat=3, atom_radius=1.2, nstates=16, block=8)
+    og, atoms, H = hamiltonian.build_system(w)
+    g = rsd.Grid.for_workload(w)
+    nl = rsd.NonLocal(g, atoms.pos, atoms.D, w.rc, w.sigma, max_states=16)
+    tv = torch.from_numpy(H.vloc).cuda()
+    rng = np.random.default_rng(5)
+    p = rng.normal(scale=0.2, size=ocnn.NP)
+    p[ocnn.NW], p[ocnn.NW + 1] = 0.3, -0.8
+    p = p.astype(np.float32).astype(np.float64)
+    psi, _, _ = linalg.orthonormalize(synthetic.draw_states(synthetic.rng_after_atoms(w), 16, og.np), og.dv)
+    opts0 = rmmdiis.Options(m=3, block=8, tol=1e-12)
+    for _ in range(6):
+        psi = rmmdiis.rmmdiis_step(H, psi, opts0)["psi"]
+    r = rmmdiis.rmmdiis_step(H, psi, opts0)["resnorm"]
+    tol = float(np.max(r[:8])) * (1.0 + 1e-6)
+    assert np.max(r[8:]) > 1.01 * tol
+    want = rmmdiis.rmmdiis_step(H, psi, rmmdiis.Options(m=3, block=8, tol=tol), net=p)
+    assert not want["active"][:8].any() and want["active"][8:].all()
+    net = rsd.Cnn(16, int(np.prod(ocnn.box_of(og)[1])))
+    net.set_params(p)
+    s = rsd.Eigensolver(g, nl, tv, 16, 8, m=3, tol=tol)
+    s.set_precond(net)
+    t = torch.from_numpy(rsd.to_blocks(psi, 8)).cuda()
+    eig, res, _ = s.step(t)
+    got = rsd.from_blocks(t.cpu().numpy())
+    st = s.stats()
+    nmix = int(np.sum(want["mix"][:, 1] != 0.0))
+    assert st["frozen_blocks"] == 1 and st["net_states"] == nmix and 0 < nmix <= 8
+    assert np.max(np.abs(eig - want["eig"])) < 1e-12 * np.max(np.abs(want["eig"]))
+    assert np.max(np.abs(res - want["resnorm"])) < 1e-10 * np.max(want["resnorm"])
+    assert np.max(np.abs(got - want["psi"])) / np.max(np.abs(want["psi"])) < 1e-6
+
+
 def test_trained_network_beats_filter():
     w, g, nl, tv, psi0 = _system()
     net = rsd.Cnn(32, g.np)
