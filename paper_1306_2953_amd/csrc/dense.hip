@@ -889,13 +889,19 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
             for (int j = lane; j < N; j += 64) A[i * ld + j] = Ag[i * N + j];
     const int M = N + (N & 1);        // even number of players (a dummy when N is odd)
     const int h = M / 2;
+    // N <= 128: rounds keep only the upper triangle up to date (each element
+    // written once, at (min, max) of its indices); larger N: both
+    const bool upper = h <= 64 && nw == 16;
     __syncthreads();
     // Frobenius norms (all entries, then off-diagonal) in a fixed order
     auto block_sum = [&](bool offdiag) {
         double loc = 0.0;
         for (int i = wave; i < N; i += nw)
-            for (int j = lane; j < N; j += 64)
-                if (!offdiag || i != j) loc += A[i * ld + j] * A[i * ld + j];
+            for (int j = lane; j < N; j += 64) {
+                const double a = A[i * ld + j];
+                if (upper && offdiag) loc += j > i ? 2.0 * (a * a) : 0.0;
+                else if (!offdiag || i != j) loc += a * a;
+            }
         loc = wave_sum(loc);
         if (lane == 0) red[wave] = loc;
         __syncthreads();
@@ -936,12 +942,14 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                 rot[((int64_t)sweep * (M - 1) + r) * h + k] = make_double2(c, s);
             }
             __syncthreads();
-            if (h <= 64 && nw == 16) {
+            if (upper) {
                 // N <= 128: a lane owns at most the four blocks (k, l) with
-                // k = wave + 16 j, l = k + lane.  A round reads only blocks
-                // l >= k and every thread writes only its own blocks and
-                // their mirrors, so all four blocks are loaded before any is
-                // stored (the loads of a round then overlap in LDS)
+                // k = wave + 16 j, l = k + lane.  A round reads and writes
+                // each element of the upper triangle once (element (a, b) at
+                // (min, max)), and only the blocks' own elements, so all four
+                // blocks are loaded before any is stored (the loads of a
+                // round then overlap in LDS)
+                auto cix = [&](int a, int b) { return a < b ? a * ld + b : b * ld + a; };
                 double x[4][4];
                 int i4[4][4];
 #pragma unroll
@@ -950,10 +958,10 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                     if (!(k < h && l < h)) continue;
                     const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
                     i4[j][0] = pk; i4[j][1] = qk; i4[j][2] = pl; i4[j][3] = ql;
-                    x[j][0] = A[pk * ld + pl];
-                    x[j][1] = ql < N ? A[pk * ld + ql] : 0.0;
-                    x[j][2] = qk < N ? A[qk * ld + pl] : 0.0;
-                    x[j][3] = qk < N && ql < N ? A[qk * ld + ql] : 0.0;
+                    x[j][0] = A[cix(pk, pl)];
+                    x[j][1] = ql < N ? A[cix(pk, ql)] : 0.0;
+                    x[j][2] = qk < N ? A[cix(qk, pl)] : 0.0;
+                    x[j][3] = qk < N && ql < N ? A[cix(qk, ql)] : 0.0;
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -970,26 +978,15 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                     if (l == k) {
                         A[pk * ld + pk] = z00;
                         if (vk) {
-                            A[pk * ld + qk] = 0.0;
-                            A[qk * ld + pk] = 0.0;
+                            A[cix(pk, qk)] = 0.0;
                             A[qk * ld + qk] = z11;
                         }
                         continue;
                     }
-                    A[pk * ld + pl] = z00;
-                    A[pl * ld + pk] = z00;
-                    if (vl) {
-                        A[pk * ld + ql] = z01;
-                        A[ql * ld + pk] = z01;
-                    }
-                    if (vk) {
-                        A[qk * ld + pl] = z10;
-                        A[pl * ld + qk] = z10;
-                    }
-                    if (vk && vl) {
-                        A[qk * ld + ql] = z11;
-                        A[ql * ld + qk] = z11;
-                    }
+                    A[cix(pk, pl)] = z00;
+                    if (vl) A[cix(pk, ql)] = z01;
+                    if (vk) A[cix(qk, pl)] = z10;
+                    if (vk && vl) A[cix(qk, ql)] = z11;
                 }
                 __syncthreads();
                 continue;
