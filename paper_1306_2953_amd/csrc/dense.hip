@@ -877,8 +877,9 @@ __global__ void __launch_bounds__(1024)
 jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, int *__restrict__ sweeps_out,
                   double2 *__restrict__ rot, double *__restrict__ diag) {
     extern __shared__ double ldsA[];
-    __shared__ double cs[128], sn[128];
-    __shared__ int pp[128], qq[128];
+    // a pair's indices and rotation, each one LDS access for the updates
+    __shared__ int2 pq[128];
+    __shared__ double2 csn[128];
     __shared__ double red[16];
     __shared__ int stop;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -938,7 +939,8 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                         s = t * c;
                     }
                 }
-                pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
+                pq[k] = make_int2(p, q);
+                csn[k] = make_double2(c, s);
                 rot[((int64_t)sweep * (M - 1) + r) * h + k] = make_double2(c, s);
             }
             __syncthreads();
@@ -956,7 +958,8 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                 for (int j = 0; j < 4; ++j) {
                     const int k = wave + 16 * j, l = k + lane;
                     if (!(k < h && l < h)) continue;
-                    const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
+                    const int2 a = pq[k], b = pq[l];
+                    const int pk = a.x, qk = a.y, pl = b.x, ql = b.y;
                     i4[j][0] = pk; i4[j][1] = qk; i4[j][2] = pl; i4[j][3] = ql;
                     x[j][0] = A[cix(pk, pl)];
                     x[j][1] = ql < N ? A[cix(pk, ql)] : 0.0;
@@ -969,7 +972,8 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                     if (!(k < h && l < h)) continue;
                     const int pk = i4[j][0], qk = i4[j][1], pl = i4[j][2], ql = i4[j][3];
                     const bool vk = qk < N, vl = ql < N;
-                    const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+                    const double2 rk = csn[k], rl = csn[l];
+                    const double ck = rk.x, sk = rk.y, cl = rl.x, sl = rl.y;
                     const double x00 = x[j][0], x01 = x[j][1], x10 = x[j][2], x11 = x[j][3];
                     const double y00 = cl * x00 - sl * x01, y01 = sl * x00 + cl * x01;
                     const double y10 = cl * x10 - sl * x11, y11 = sl * x10 + cl * x11;
@@ -992,13 +996,13 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                 continue;
             }
             for (int k = wave; k < h; k += nw) {
-                const int pk = pp[k], qk = qq[k];
+                const int pk = pq[k].x, qk = pq[k].y;
                 const bool vk = qk < N;
-                const double ck = cs[k], sk = sn[k];
+                const double ck = csn[k].x, sk = csn[k].y;
                 for (int l = k + lane; l < h; l += 64) {
-                    const int pl = pp[l], ql = qq[l];
+                    const int pl = pq[l].x, ql = pq[l].y;
                     const bool vl = ql < N;
-                    const double cl = cs[l], sl = sn[l];
+                    const double cl = csn[l].x, sl = csn[l].y;
                     const double x00 = A[pk * ld + pl];
                     const double x01 = vl ? A[pk * ld + ql] : 0.0;
                     const double x10 = vk ? A[qk * ld + pl] : 0.0;
