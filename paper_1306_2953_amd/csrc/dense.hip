@@ -131,6 +131,239 @@ gram_f64_kernel(const double *__restrict__ X, const double *__restrict__ Y, int6
     }
 }
 
+// ------------------------------------------ Gram FP64, 4 blocks of 32 states
+// Register-fed form for N = 128 in blocks of B = 32 (the eigensolver's
+// shape).  A lane reads 16 bytes of a point row: states 2m and 2m + 1 of one
+// block (m = lane % 16) at point 4t + lane / 16 of k-step t, so a wave's
+// load covers 4 whole rows.  The even and the odd states of block b act as
+// two 16-state tiles, 2b and 2b + 1: one load feeds both MFMA fragments, and
+// no LDS stage or barrier is needed.  Loads run kGramDepth k-steps ahead of
+// the MFMAs that use them.  Reads past the chunk's end come back as zeros
+// (buffer bounds), so every chunk runs whole groups of k-steps.
+//  - symmetric (X == Y): two waves per chunk; each reads all four blocks
+//    and owns 18 of the 36 tile pairs t1 <= t2 (lists 0 and 1);
+//  - general: four waves per chunk; wave w reads X blocks 2(w/2), 2(w/2)+1
+//    and Y blocks 2(w%2), 2(w%2)+1 and owns their 16 tile pairs (list 2,
+//    fragments 0-3 from X, 4-7 from Y).
+// A fragment index f names register half f % 2 of the load from block slot
+// f / 2.  The partial of tile pair (t1, t2) holds entry (i, j), i in tile t1.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+constexpr int kGramDepth = 4;
+constexpr int kGramPairs[3][18][2] = {
+    {{0, 0}, {0, 1}, {1, 1}, {2, 2}, {2, 3}, {3, 3}, {0, 2}, {0, 3}, {1, 2},
+     {1, 3}, {4, 6}, {4, 7}, {5, 6}, {5, 7}, {0, 4}, {0, 5}, {1, 4}, {1, 5}},
+    {{4, 4}, {4, 5}, {5, 5}, {6, 6}, {6, 7}, {7, 7}, {0, 6}, {0, 7}, {1, 6},
+     {1, 7}, {2, 4}, {2, 5}, {3, 4}, {3, 5}, {2, 6}, {2, 7}, {3, 6}, {3, 7}},
+    {{0, 4}, {0, 5}, {0, 6}, {0, 7}, {1, 4}, {1, 5}, {1, 6}, {1, 7},
+     {2, 4}, {2, 5}, {2, 6}, {2, 7}, {3, 4}, {3, 5}, {3, 6}, {3, 7}, {0, 0}, {0, 0}}};
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void gram_r32_load(const rsrc_t (&rs)[4], uint32_t lane_off, int t, d2 (&b)[4]) {
+    const int off = (int)(lane_off + (uint32_t)t * 1024u);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        b[f] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs[f], off, 0, 0));
+}
+// The first kGramDepth k-steps' loads are issued by the caller (before any
+// branch on the wave's list, so that they stay in k-step order).  The
+// scheduler barriers keep the loads in that order, so the wait before a
+// step's MFMAs leaves the later steps' loads in flight.
+template <int L, int NP>
+__device__ __forceinline__ void gram_r32_wave(const rsrc_t (&rs)[4], int nk, uint32_t lane_off,
+                                              d2 (&buf)[kGramDepth][4], const int (&tile)[8],
+                                              double *__restrict__ out) {
+    d4 acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] = d4{0, 0, 0, 0};
+    for (int t0 = 0; t0 < nk; t0 += kGramDepth) {
+#pragma unroll
+        for (int j = 0; j < kGramDepth; ++j) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const int f1 = kGramPairs[L][i][0], f2 = kGramPairs[L][i][1];
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[j][f1 >> 1][f1 & 1], buf[j][f2 >> 1][f2 & 1],
+                                                              acc[i], 0, 0, 0);
+            }
+            gram_r32_load(rs, lane_off, t0 + j + kGramDepth, buf[j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    const int g = (int)(threadIdx.x & 63) >> 4, m = threadIdx.x & 15;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int t1 = tile[kGramPairs[L][i][0]], t2 = tile[kGramPairs[L][i][1]];
+        const int col = (t2 >> 1) * 32 + 2 * m + (t2 & 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            out[((t1 >> 1) * 32 + 2 * (4 * r + g) + (t1 & 1)) * 128 + col] = acc[i][r];
+    }
+}
+
+template <bool SYRK>
+__global__ void __launch_bounds__(SYRK ? 128 : 256) __attribute__((amdgpu_waves_per_eu(2)))
+gram_f64_r32_kernel(const double *__restrict__ X, const double *__restrict__ Y, int64_t np, int64_t CP,
+                    double *__restrict__ partial) {
+    const int chunk = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t p_beg = (int64_t)chunk * CP;
+    const int64_t npts = min<int64_t>(np, p_beg + CP) - p_beg;
+    const uint32_t bytes = (uint32_t)(npts * 256);
+    const int nk = (int)((npts + 4 * kGramDepth - 1) / (4 * kGramDepth)) * kGramDepth;
+    const uint32_t lane_off = (uint32_t)((lane >> 4) * 256 + (lane & 15) * 16);
+    double *out = partial + (int64_t)chunk * 128 * 128;
+    rsrc_t rs[4];
+    int tile[8];
+    if constexpr (SYRK) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rs[f] = make_rsrc(X + (f * np + p_beg) * 32, bytes);
+#pragma unroll
+        for (int f = 0; f < 8; ++f) tile[f] = f;
+    } else {
+        const int xa = 2 * (wave >> 1), yb = 2 * (wave & 1);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            rs[f] = make_rsrc(X + ((xa + f) * np + p_beg) * 32, bytes);
+            rs[2 + f] = make_rsrc(Y + ((yb + f) * np + p_beg) * 32, bytes);
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            tile[f] = 2 * xa + f;
+            tile[4 + f] = 2 * yb + f;
+        }
+    }
+    d2 buf[kGramDepth][4];
+#pragma unroll
+    for (int j = 0; j < kGramDepth; ++j) {
+        gram_r32_load(rs, lane_off, j, buf[j]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (SYRK) {
+        if (wave == 0) gram_r32_wave<0, 18>(rs, nk, lane_off, buf, tile, out);
+        else gram_r32_wave<1, 18>(rs, nk, lane_off, buf, tile, out);
+    } else {
+        gram_r32_wave<2, 16>(rs, nk, lane_off, buf, tile, out);
+    }
+}
+
+// ------------------------------------ Gram BF16x3, 4 blocks of 32 states
+// The FP32 form of the register-fed product above (the same even / odd
+// state tiles).  MFMA bf16 16x16x32 takes 8 k-values per lane: lane (g, m),
+// g = lane / 16, reads states 2m and 2m + 1 of a block (8 bytes) at points
+// 32t + 8g + s, s = 0..7, of k-step t, and splits each value x into bf16
+// hi = rn(x) and lo = rn(x - hi) in registers.  A tile pair's four products
+// hi.hi, hi.lo, lo.hi and lo.lo of one k-step are summed in FP32 on the
+// matrix core and added to an FP64 accumulator, so the running sums carry
+// no FP32 rounding.  With FP64 accumulators a wave holds 9 tile pairs:
+//  - symmetric: four waves per chunk, lists 0-3 (each within three blocks;
+//    the loads of a block a list does not use are dropped by the compiler);
+//  - general: eight waves per chunk; wave w reads X block w / 2 (fragments
+//    0, 1) and Y blocks 2(w%2), 2(w%2)+1 (fragments 4-7): 8 tile pairs.
+// The next k-step's loads are in flight while the current one is split and
+// multiplied.
+constexpr int kGramBfPairs[5][9][2] = {
+    {{0, 0}, {0, 1}, {1, 1}, {2, 2}, {2, 3}, {3, 3}, {4, 4}, {4, 5}, {5, 5}},
+    {{6, 6}, {6, 7}, {7, 7}, {0, 6}, {0, 7}, {1, 6}, {1, 7}, {2, 6}, {2, 7}},
+    {{0, 2}, {0, 3}, {1, 2}, {1, 3}, {0, 4}, {0, 5}, {1, 4}, {1, 5}, {2, 4}},
+    {{2, 5}, {3, 4}, {3, 5}, {4, 6}, {4, 7}, {5, 6}, {5, 7}, {3, 6}, {3, 7}},
+    {{0, 4}, {0, 5}, {0, 6}, {0, 7}, {1, 4}, {1, 5}, {1, 6}, {1, 7}, {0, 0}}};
+
+template <int L, int NP>
+__device__ __forceinline__ void gram_bf_r32_wave(const rsrc_t (&rs)[4], int nk, uint32_t lane_off,
+                                                 const int (&tile)[8], double *__restrict__ out) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 raw[4][8];
+    d4 acc[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) acc[i] = d4{0, 0, 0, 0};
+    auto load = [&](int t) {
+        const uint32_t off = lane_off + (uint32_t)t * 4096u;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                raw[f][k] = __builtin_bit_cast(
+                    f2, __builtin_amdgcn_raw_buffer_load_b64(rs[f], (int)(off + (uint32_t)k * 128u), 0, 0));
+    };
+    load(0);
+    for (int t = 0; t < nk; ++t) {
+        bf8 hi[8], lo[8];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float x = raw[f][k][e];
+                    const __bf16 h = (__bf16)x;
+                    hi[2 * f + e][k] = h;
+                    lo[2 * f + e][k] = (__bf16)(x - (float)h);
+                }
+        load(t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int f1 = kGramBfPairs[L][i][0], f2 = kGramBfPairs[L][i][1];
+            f4 p = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[f1], lo[f2], f4{0, 0, 0, 0}, 0, 0, 0);
+            p = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[f1], lo[f2], p, 0, 0, 0);
+            p = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[f1], hi[f2], p, 0, 0, 0);
+            p = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[f1], hi[f2], p, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][r] += (double)p[r];
+        }
+    }
+    const int g = (int)(threadIdx.x & 63) >> 4, m = threadIdx.x & 15;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int t1 = tile[kGramBfPairs[L][i][0]], t2 = tile[kGramBfPairs[L][i][1]];
+        const int col = (t2 >> 1) * 32 + 2 * m + (t2 & 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            out[((t1 >> 1) * 32 + 2 * (4 * g + r) + (t1 & 1)) * 128 + col] = acc[i][r];
+    }
+}
+
+template <bool SYRK>
+__global__ void __launch_bounds__(SYRK ? 256 : 512) __attribute__((amdgpu_waves_per_eu(2)))
+gram_bf_r32_kernel(const float *__restrict__ X, const float *__restrict__ Y, int64_t np, int64_t CP,
+                   double *__restrict__ partial) {
+    const int chunk = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t p_beg = (int64_t)chunk * CP;
+    const int64_t npts = min<int64_t>(np, p_beg + CP) - p_beg;
+    const uint32_t bytes = (uint32_t)(npts * 128);
+    const int nk = (int)((npts + 31) / 32);
+    const uint32_t lane_off = (uint32_t)((lane >> 4) * 8 * 128 + (lane & 15) * 8);
+    double *out = partial + (int64_t)chunk * 128 * 128;
+    rsrc_t rs[4];
+    int tile[8];
+    if constexpr (SYRK) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rs[f] = make_rsrc(X + (f * np + p_beg) * 32, bytes);
+#pragma unroll
+        for (int f = 0; f < 8; ++f) tile[f] = f;
+        if (wave == 0) gram_bf_r32_wave<0, 9>(rs, nk, lane_off, tile, out);
+        else if (wave == 1) gram_bf_r32_wave<1, 9>(rs, nk, lane_off, tile, out);
+        else if (wave == 2) gram_bf_r32_wave<2, 9>(rs, nk, lane_off, tile, out);
+        else gram_bf_r32_wave<3, 9>(rs, nk, lane_off, tile, out);
+    } else {
+        const int xa = wave >> 1, yb = 2 * (wave & 1);
+        rs[0] = rs[1] = make_rsrc(X + (xa * np + p_beg) * 32, bytes);
+        rs[2] = make_rsrc(Y + (yb * np + p_beg) * 32, bytes);
+        rs[3] = make_rsrc(Y + ((yb + 1) * np + p_beg) * 32, bytes);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            tile[f] = 2 * xa + (f & 1);
+            tile[4 + f] = 2 * yb + f;
+        }
+        gram_bf_r32_wave<4, 8>(rs, nk, lane_off, tile, out);
+    }
+}
+
 // ---------------------------------------------------------- Gram BF16x3
 // FP32 data split as hi + lo (bfloat16 each); a.b ~ hi.hi + hi.lo + lo.hi
 // summed on MFMA 16x16x32 per 32-point stage and accumulated in FP64, plus
@@ -280,6 +513,9 @@ gram_reduce2_kernel(const double *__restrict__ red, int ng, int N, int N16, int 
     double v;
     if (mode == 1) {
         const bool up = i / 16 <= j / 16;
+        v = sum(up ? i : j, up ? j : i);
+    } else if (mode == 3) {     // tiles of the even / odd states of 32-state blocks
+        const bool up = 2 * (i / 32) + (i & 1) <= 2 * (j / 32) + (j & 1);
         v = sum(up ? i : j, up ? j : i);
     } else if (mode == 2) {
         v = 0.5 * (sum(i, j) + sum(j, i));
@@ -1178,6 +1414,21 @@ rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, in
     return e;
 }
 
+// Sum of the chunk partials into S (reduce mode as in gram_reduce2_kernel).
+static rs_status gram_reduce(const GramScratch &w, int nchunks, int N, int N16, int rmode, double dv, double *S,
+                             hipStream_t st) {
+    const int64_t ne = (int64_t)N16 * N16;
+    const int ng = std::min(kRedGroups, nchunks);
+    const int cpg = (nchunks + ng - 1) / ng;
+    hipLaunchKernelGGL(gram_reduce1_kernel, dim3((unsigned)((ne + 255) / 256), ng), dim3(256), 0, st, w.partial,
+                       nchunks, cpg, ne, w.red);
+    RS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(gram_reduce2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, w.red, ng, N, N16, rmode,
+                       dv, S);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
 rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const void *Y, int64_t np, int B,
                     int nblk, int dtype, int prec, double dv, double *S, int mode, hipStream_t st) {
     const int N = nblk * B;
@@ -1195,6 +1446,46 @@ rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const 
     const int nsplit = (nblocks + per_wg - 1) / per_wg;
     const int bps = (nblocks + nsplit - 1) / nsplit;
     const bool bf = dtype == RS_F32 && prec == RS_PREC_BF16X3;
+    if (bf && B == 32 && N == 128) {
+        // about two waves per SIMD: 512 chunks of four waves (symmetric) or
+        // 256 of eight, in whole 32-point k-steps, bounded by the workspace
+        const int64_t want = syrk ? 512 : 256;
+        int64_t CP = std::max<int64_t>((np + want - 1) / want, (np + w.max_chunks - 1) / w.max_chunks);
+        CP = std::max<int64_t>(32, (CP + 31) / 32 * 32);
+        const int nchunks = (int)((np + CP - 1) / CP);
+        if ((int64_t)nchunks * 128 * 128 * (int64_t)sizeof(double) > w.partial_bytes)
+            return fail(RS_EINVAL, "gram: workspace too small");
+        if (CP * 128 > INT32_MAX) return fail(RS_EINVAL, "gram: chunk too large for 32-bit offsets");
+        if (syrk)
+            hipLaunchKernelGGL(gram_bf_r32_kernel<true>, dim3(nchunks), dim3(256), 0, st, (const float *)X,
+                               (const float *)Y, np, CP, w.partial);
+        else
+            hipLaunchKernelGGL(gram_bf_r32_kernel<false>, dim3(nchunks), dim3(512), 0, st, (const float *)X,
+                               (const float *)Y, np, CP, w.partial);
+        RS_HIP(hipGetLastError());
+        return gram_reduce(w, nchunks, N, N16, syrk ? 3 : mode, dv, S, st);
+    }
+    if (dtype == RS_F64 && B == 32 && N == 128) {
+        // about two waves per SIMD: 1024 chunks of two waves (symmetric) or
+        // 512 of four, each a whole number of load groups of 4 * kGramDepth
+        // points, bounded by the partial-sum workspace
+        const int64_t group = 4 * kGramDepth;
+        int64_t CP = std::max<int64_t>((np + (syrk ? 1023 : 511)) / (syrk ? 1024 : 512),
+                                       (np + w.max_chunks - 1) / w.max_chunks);
+        CP = std::max<int64_t>(group, (CP + group - 1) / group * group);
+        const int nchunks = (int)((np + CP - 1) / CP);
+        if ((int64_t)nchunks * 128 * 128 * (int64_t)sizeof(double) > w.partial_bytes)
+            return fail(RS_EINVAL, "gram: workspace too small");
+        if (CP * 256 > INT32_MAX) return fail(RS_EINVAL, "gram: chunk too large for 32-bit offsets");
+        if (syrk)
+            hipLaunchKernelGGL(gram_f64_r32_kernel<true>, dim3(nchunks), dim3(128), 0, st, (const double *)X,
+                               (const double *)Y, np, CP, w.partial);
+        else
+            hipLaunchKernelGGL(gram_f64_r32_kernel<false>, dim3(nchunks), dim3(256), 0, st, (const double *)X,
+                               (const double *)Y, np, CP, w.partial);
+        RS_HIP(hipGetLastError());
+        return gram_reduce(w, nchunks, N, N16, syrk ? 3 : mode, dv, S, st);
+    }
     // small chunks: several work-groups per compute unit (each owns all
     // output blocks of its chunk), bounded by the partial-sum workspace
     int64_t CP = bf ? 1024 : 512;
@@ -1238,19 +1529,7 @@ rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const 
         return fail(RS_ENOTSUP, "gram: FP32 data needs RS_PREC_BF16X3");
     }
     RS_HIP(hipGetLastError());
-    const int rmode = syrk ? 1 : mode;
-    {
-        const int64_t ne = (int64_t)N16 * N16;
-        const int ng = std::min(kRedGroups, nchunks);
-        const int cpg = (nchunks + ng - 1) / ng;
-        hipLaunchKernelGGL(gram_reduce1_kernel, dim3((unsigned)((ne + 255) / 256), ng), dim3(256), 0, st,
-                           w.partial, nchunks, cpg, ne, w.red);
-        RS_HIP(hipGetLastError());
-        hipLaunchKernelGGL(gram_reduce2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, w.red, ng,
-                           N, N16, rmode, dv, S);
-    }
-    RS_HIP(hipGetLastError());
-    return RS_OK;
+    return gram_reduce(w, nchunks, N, N16, syrk ? 1 : mode, dv, S, st);
 }
 
 rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, int nblk, int dtype, int prec,
