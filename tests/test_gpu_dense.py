@@ -35,8 +35,10 @@ def _blk(states, B):
     return _dev(rsd.to_blocks(states, B))
 
 
-@pytest.mark.parametrize("nblk,B", [(3, 32), (1, 8), (5, 8), (2, 64), (16, 16)])
+@pytest.mark.parametrize("nblk,B", [(4, 32), (3, 32), (1, 8), (5, 8), (2, 64), (16, 16)])
 def test_overlap_fp64(small, nblk, B):
+    """(4, 32) runs the register-fed products (chunks of 16 points here, the
+    last one ragged); the other shapes the LDS-staged ones."""
     w, og, H, g, ctx = small
     rng = np.random.default_rng(B + nblk)
     x = rng.uniform(-1, 1, (nblk * B, og.np))
@@ -58,8 +60,8 @@ def test_overlap_fp64(small, nblk, B):
 @pytest.mark.parametrize("nblk,B", [(4, 32), (1, 8), (3, 16)])
 def test_overlap_bf16x3_error_bound(small, nblk, B):
     """Split-BF16 products: |error| <= 2^-16 h^3 sum_p |x_p y_p| elementwise
-    (two-term splits leave 2^-17 |x y| per product; FP32 accumulation over
-    chunks of at most 4096 points, summed in FP64)."""
+    (two-term splits leave 2^-17 |x y| per product; each MFMA step sums at
+    most 32 points in FP32, the steps are accumulated in FP64)."""
     w, og, H, g, ctx = small
     rng = np.random.default_rng(7 + B)
     x = rng.uniform(-1, 1, (nblk * B, og.np)).astype(np.float32)
@@ -209,11 +211,15 @@ def test_full_size_overlap():
     ctx = rsd.Context(g, 128)
     x = synthetic.draw_states(synthetic.rng_after_atoms(w), 128, g.np)
     want = linalg.overlap(x, g.dv)
-    S = ctx.overlap(_blk(x, 32), _blk(x, 32)).cpu().numpy()
-    assert np.max(np.abs(S - want)) <= 1e-12 * np.max(np.abs(want))
+    tx = _blk(x, 32)
+    for a, b in ((tx, _blk(x, 32)), (tx, tx)):          # general, then symmetric
+        S = ctx.overlap(a, b).cpu().numpy()
+        assert np.max(np.abs(S - want)) <= 1e-12 * np.max(np.abs(want))
     x32 = x.astype(np.float32)
-    S32 = ctx.overlap(_blk(x32, 32), _blk(x32, 32)).cpu().numpy()
     x64 = x32.astype(np.float64)
     want32 = linalg.overlap(x64, g.dv)
     bound = 2.0 ** -16 * g.dv * np.abs(x64) @ np.abs(x64).T
-    assert np.all(np.abs(S32 - want32) <= bound)
+    t32 = _blk(x32, 32)
+    for a, b in ((t32, _blk(x32, 32)), (t32, t32)):
+        S32 = ctx.overlap(a, b).cpu().numpy()
+        assert np.all(np.abs(S32 - want32) <= bound)
