@@ -575,21 +575,25 @@ hpsi_march_kernel(const MarchChunk *__restrict__ chunks, const MarchBrick *__res
 // spheres holding the point of gamma_A,i(p) (D_A,i P_A,i), i < NPJ, one lane
 // per (state, point) of the points that lie in a sphere (eq. 6).  A lane
 // serves up to 4 blocks: the entry loads are shared and the 4 updates are
-// independent.
+// independent; the H psi values are read before the entries, so their
+// latency overlaps the entry loads.  nnl * B < 2^32 (checked by the host).
 template <typename T, int NPJ>
 __global__ void __launch_bounds__(256)
 nl_add_kernel(const int32_t *__restrict__ nl_pts, int64_t nnl, const int32_t *__restrict__ pt_ptr,
               const int32_t *__restrict__ ent_atom, const T *__restrict__ ent_gamma, const T *__restrict__ dp,
               T *__restrict__ hpsi, int64_t np, int B, int nat, int nblk) {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= nnl * B) return;
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if ((int64_t)idx >= nnl * B) return;
     const int blk0 = 4 * blockIdx.y;
     const int nb = min(4, nblk - blk0);
-    const int p = nl_pts[idx / B];
-    const int s = (int)(idx % B);
+    const int p = nl_pts[idx / (uint32_t)B];
+    const int s = (int)(idx % (uint32_t)B);
     const int64_t dstride = (int64_t)nat * NPJ * B;
     const T *dpl = dp + blk0 * dstride + s;
-    T acc[4] = {T(0), T(0), T(0), T(0)};
+    T acc[4] = {T(0), T(0), T(0), T(0)}, y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < nb) y[k] = hpsi[((int64_t)(blk0 + k) * np + p) * B + s];
     for (int e = pt_ptr[p], e1 = pt_ptr[p + 1]; e < e1; ++e) {
         T g[NPJ];
 #pragma unroll
@@ -607,10 +611,7 @@ nl_add_kernel(const int32_t *__restrict__ nl_pts, int64_t nnl, const int32_t *__
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (k < nb) {
-            T *y = hpsi + ((int64_t)(blk0 + k) * np + p) * B + s;
-            *y += acc[k];
-        }
+        if (k < nb) hpsi[((int64_t)(blk0 + k) * np + p) * B + s] = y[k] + acc[k];
 }
 
 // Non-local part 1 (eq. 6 integrals), stage 1: one work-group per (chunk of
@@ -749,6 +750,8 @@ rs_status launch_project(const rs_grid *g, const rs_nl *nl, const T *psi, T *pro
 template <typename T>
 rs_status launch_nl_add(const rs_grid *g, const rs_nl *nl, T *hpsi, int nblk, int B, hipStream_t st) {
     if (nl->nnlpts == 0) return RS_OK;
+    if ((int64_t)nl->nnlpts * B > (int64_t)UINT32_MAX - 255)
+        return fail(RS_EINVAL, "stencil: too many projector points x states for one launch");
     const T *egm = sizeof(T) == 8 ? (const T *)nl->ent_gamma64.p : (const T *)nl->ent_gamma32.p;
     dim3 gn((unsigned)((nl->nnlpts * B + 255) / 256), (nblk + 3) / 4);
 #define RS_NLADD(NPJ)                                                                                   \
