@@ -66,8 +66,9 @@ typedef int rs_status;
  * accumulation of the split-K partial sums.  RS_PREC_BF16X3: FP32 fields
  * split as a = a_hi + a_lo (each bfloat16, round to nearest even); products
  * on matrix cores with FP32 accumulation.  Overlaps: a_hi b_hi + a_hi b_lo +
- * a_lo b_hi + a_lo b_lo (the last keeps norms unbiased), partial sums over
- * chunks of <= 4096 points added in FP64.  Rotations: field and FP64 matrix
+ * a_lo b_hi + a_lo b_lo (the last keeps norms unbiased) summed in FP32 over
+ * at most 32 points per matrix-core step, the steps accumulated in FP64.
+ * Rotations: field and FP64 matrix
  * are both split in three bfloat16 terms and the six products a_i x_j with
  * i + j <= 2 are summed in FP32, which keeps the rotated field at FP32
  * accuracy. */
@@ -224,8 +225,10 @@ void rs_ctx_destroy(rs_ctx *c);
 /* Eq. (7) generalised: S[j][k] = h^3 sum_p X[p][j] Y[p][k] for N = nblk*B
  * states stored in the block layout; S is DEVICE double [N][N].  When x == y
  * only the upper 16x16 blocks are formed (symmetric rank-k product) and
- * mirrored.  Per-chunk (<= 4096 points) partial sums are added in FP64 in a
- * fixed order (bitwise repeatable).  prec must be RS_PREC_NATIVE for RS_F64
+ * mirrored.  The points are split in chunks (a few hundred to a few
+ * thousand points each, set by the grid and the shape); the chunks' partial
+ * sums are added in FP64 in a fixed order (bitwise repeatable for a given
+ * grid and shape).  prec must be RS_PREC_NATIVE for RS_F64
  * and RS_PREC_BF16X3 for RS_F32 (else RS_ENOTSUP).  Complex states (RS_C128
  * with RS_PREC_NATIVE, RS_C64 with RS_PREC_BF16X3): S is DEVICE complex
  * double [N][N] (re, im interleaved), S[j][k] = h^3 sum_p conj(X[p][j])
@@ -240,10 +243,10 @@ rs_status rs_overlap(rs_ctx *c, const void *x, const void *y, double *S, int32_t
  * partial sums, group sums and block lists live in a fixed 64 MiB device
  * array that the library holds on each GPU it runs on until the process
  * ends; the call performs no allocation of any kind.  Limits: N = nblk*B in
- * [1, 256] (else RS_EINVAL); the points per chunk grow past 4096 when the
- * array holds fewer partial sums than the grid has 4096-point chunks (for
- * 256 states, grids above about 450k points; for 128, above 2M), which
- * changes only the rounding.  Every call on a GPU uses that GPU's one
+ * [1, 256] (else RS_EINVAL); the chunks grow when the array holds fewer
+ * partial sums than rs_overlap would use (for 256 states, grids above about
+ * 450k points), which changes only the rounding.  Every call on a GPU uses
+ * that GPU's one
  * array, whose contents the last call leaves behind (nothing in it needs to
  * start at zero): calls that overlap in time on one GPU (any streams, any
  * threads) race and give wrong results.  The array's device address is
