@@ -45,8 +45,9 @@ def test_noalloc_overlap_matches_context_overlap(dtype):
                 assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
                 assert np.max(np.abs(got - dv * (A.T @ Bm))) <= 1e-12 * np.max(np.abs(want))
             else:
-                # both are split-BF16 products with FP32 chunk sums: each within
-                # 2^-16 sum|ab| of the exact product of the FP32 inputs
+                # both are split-BF16 products (FP32 sums of at most 32 points,
+                # accumulated in FP64): each within 2^-16 sum|ab| of the exact
+                # product of the FP32 inputs
                 exact = dv * (A.T @ Bm)
                 assert np.all(np.abs(got - exact) <= 2.0 ** -16 * scale)
                 assert np.all(np.abs(got - want) <= 2.0 ** -15 * scale)
