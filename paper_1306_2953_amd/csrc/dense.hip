@@ -1148,6 +1148,22 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
         return t;
     };
     const double fro = sqrt(block_sum(false));
+    // N <= 128: rows a = P and h - 1 - P of the upper triangle of 2x2 blocks
+    // hold h + 1 blocks together, so wave w takes the row pairs P = w and
+    // w + 16 (one block per lane each, the 65th on lanes 0 and 1): at most
+    // three blocks (k, l) per lane, the same in every round
+    int kl[3][2];
+    bool on[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int P = j < 2 ? wave + 16 * j : wave + 16 * lane;
+        const int c = j < 2 ? lane : 64;
+        const int a = P, b = h - 1 - P;
+        const int na = h - a, nt = a < b ? h + 1 : na;
+        on[j] = upper && a <= b && c < nt && (j < 2 || lane < 2);
+        kl[j][0] = c < na ? a : b;
+        kl[j][1] = c < na ? a + c : b + (c - na);
+    }
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
         const double off = sqrt(block_sum(true));
@@ -1181,31 +1197,19 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
             }
             __syncthreads();
             if (upper) {
-                // N <= 128: rows a = P and h - 1 - P of the upper triangle of
-                // 2x2 blocks hold h + 1 blocks together, so wave w takes the
-                // row pairs P = w and w + 16 (one block per lane each, the
-                // 65th on lanes 0 and 1): at most three blocks per lane.  A
-                // round reads and writes each element of the upper triangle
+                // a round reads and writes each element of the upper triangle
                 // once (element (a, b) at (min, max)), and only the blocks'
                 // own elements, so all blocks are loaded before any is
                 // stored (the loads of a round then overlap in LDS)
                 auto cix = [&](int a, int b) { return a < b ? a * ld + b : b * ld + a; };
                 double x[3][4];
-                int kl[3][2];
-                bool on[3];
+                int4 ix[3];
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const int P = j < 2 ? wave + 16 * j : wave + 16 * lane;
-                    const int c = j < 2 ? lane : 64;
-                    const int a = P, b = h - 1 - P;
-                    const int na = h - a, nt = a < b ? h + 1 : na;
-                    on[j] = a <= b && c < nt && (j < 2 || lane < 2);
-                    const int k = c < na ? a : b, l = c < na ? a + c : b + (c - na);
-                    kl[j][0] = k;
-                    kl[j][1] = l;
                     if (!on[j]) continue;
-                    const int2 u = pq[k], v = pq[l];
+                    const int2 u = pq[kl[j][0]], v = pq[kl[j][1]];
                     const int pk = u.x, qk = u.y, pl = v.x, ql = v.y;
+                    ix[j] = make_int4(pk, qk, pl, ql);
                     x[j][0] = A[cix(pk, pl)];
                     x[j][1] = ql < N ? A[cix(pk, ql)] : 0.0;
                     x[j][2] = qk < N ? A[cix(qk, pl)] : 0.0;
@@ -1215,8 +1219,7 @@ jacobi_rot_kernel(double *__restrict__ Ag, int N, int max_sweeps, double tol, in
                 for (int j = 0; j < 3; ++j) {
                     if (!on[j]) continue;
                     const int k = kl[j][0], l = kl[j][1];
-                    const int2 u = pq[k], v = pq[l];
-                    const int pk = u.x, qk = u.y, pl = v.x, ql = v.y;
+                    const int pk = ix[j].x, qk = ix[j].y, pl = ix[j].z, ql = ix[j].w;
                     const bool vk = qk < N, vl = ql < N;
                     const double2 rk = csn[k], rl = csn[l];
                     const double ck = rk.x, sk = rk.y, cl = rl.x, sl = rl.y;
