@@ -113,7 +113,8 @@ rs_status orthonormalize_impl(rs_ctx *c, void *psi, int nblk, int B, int dtype, 
     if ((st = rs::pad_identity(S, N, nreal, s))) return st;
     if ((st = rs::cholesky(c->w, S, c->U.as<double>(), N, c->info.as<int>(), s))) return st;
     if ((st = rs::trinv(c->U.as<double>(), c->T.as<double>(), N, c->info.as<int>(), s))) return st;
-    if ((st = rs::rotate(c->w, psi, c->T.as<double>(), c->g->np, B, nblk, dtype, prec, c->info.as<int>(), s)))
+    if ((st = rs::rotate(c->w, psi, c->T.as<double>(), c->g->np, B, nblk, dtype, prec, c->info.as<int>(), s,
+                         true)))
         return st;
     int h_info = 0;
     RS_HIP(hipMemcpyAsync(&h_info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -682,7 +682,7 @@ constexpr int kRotXLds = 128 * (128 + kRotPad) * 8;
 template <int MT>
 __global__ void __launch_bounds__(512)
 rotate_f64_px_kernel(double *__restrict__ psi, const double *__restrict__ Xm, int64_t np, int B, int N, int ncb,
-                     int64_t ntiles, const int *__restrict__ skip) {
+                     int64_t ntiles, const int *__restrict__ skip, int upper) {
     constexpr int MAXC = 8;
     extern __shared__ double xs[];              // [N16][ncb * 16 + kRotPad]
     if (skip && *skip) return;
@@ -710,7 +710,9 @@ rotate_f64_px_kernel(double *__restrict__ psi, const double *__restrict__ Xm, in
             const int r = 16 * kb + 4 * j + i;
 #pragma unroll
             for (int c = 0; c < MAXC; ++c) {
-                if (c < ncb) {
+                // upper-triangular X (the inverse Cholesky factor): its
+                // 16 x 16 blocks below the diagonal are zero
+                if (c < ncb && !(upper && c < kb)) {
                     const double b = xs[r * ld + c * 16 + pl];
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
@@ -1546,7 +1548,7 @@ rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const 
 }
 
 rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, int nblk, int dtype, int prec,
-                 const int *skip, hipStream_t st) {
+                 const int *skip, hipStream_t st, bool upper) {
     const int N = nblk * B;
     const int N16 = (N + 15) / 16 * 16;
     const int ncb = N16 / 16;
@@ -1566,7 +1568,7 @@ rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, i
             const size_t xl = (size_t)N16 * (N16 + kRotPad) * sizeof(double);
             const unsigned grid = (unsigned)std::min<int64_t>(ntiles, std::max(w.ncu, 1));
             hipLaunchKernelGGL((rotate_f64_px_kernel<kRotMT>), dim3(grid), dim3(512), xl, st, (double *)psi, Xm, np,
-                               B, N, ncb, ntiles, skip);
+                               B, N, ncb, ntiles, skip, upper ? 1 : 0);
         } else if (B % 16 == 0) {
             // ncb > 8 here: the persistent kernel above takes the rest
             hipLaunchKernelGGL((rotate_f64_vec_kernel<1, MAXC64>), dim3((unsigned)((np + 127) / 128)), dim3(512),

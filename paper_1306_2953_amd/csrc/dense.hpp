@@ -45,8 +45,10 @@ rs_status gram_core(const GramScratch &w, bool make_lists, const void *X, const 
 rs_status gram(DenseWork &w, const void *X, const void *Y, int64_t np, int B, int nblk, int dtype,
                int prec, double dv, double *S, int mode, hipStream_t st);
 // psi <- psi X in place (skipped when *skip != 0, if skip is given).
+// upper: X is upper triangular (exact zeros below the diagonal), which the
+// FP64 kernel for N <= 128 uses to skip the zero blocks.
 rs_status rotate(DenseWork &w, void *psi, const double *Xm, int64_t np, int B, int nblk, int dtype,
-                 int prec, const int *skip, hipStream_t st);
+                 int prec, const int *skip, hipStream_t st, bool upper = false);
 rs_status cholesky(DenseWork &w, const double *S, double *U, int N, int *info_dev, hipStream_t st);
 rs_status trinv(const double *U, double *T, int N, const int *info_dev, hipStream_t st);
 // Jacobi eigensolver for a symmetric A (overwritten); max_sweeps (at most
