@@ -223,3 +223,25 @@ def test_full_size_overlap():
     for a, b in ((t32, _blk(x32, 32)), (t32, t32)):
         S32 = ctx.overlap(a, b).cpu().numpy()
         assert np.all(np.abs(S32 - want32) <= bound)
+
+
+@pytest.mark.parametrize("radius", [0.3, 0.7])
+def test_overlap_tiny_grid_4x32(radius):
+    """128 states in blocks of 32 (the register-fed products) on grids of a
+    few dozen points: one ragged chunk, most of a k-step past the end."""
+    g = rsd.Grid("sphere", 0.2, radius=radius)
+    assert 0 < g.np < 1000
+    ctx = rsd.Context(g, 128)
+    rng = np.random.default_rng(int(radius * 10))
+    for dtype in (np.float64, np.float32):
+        x = rng.uniform(-1, 1, (128, g.np)).astype(dtype)
+        y = rng.uniform(-1, 1, (128, g.np)).astype(dtype)
+        x64, y64 = x.astype(np.float64), y.astype(np.float64)
+        tx = _blk(x, 32)
+        for a, b, want, scale in ((tx, tx, x64 @ x64.T, np.abs(x64) @ np.abs(x64).T),
+                                  (tx, _blk(y, 32), x64 @ y64.T, np.abs(x64) @ np.abs(y64).T)):
+            S = ctx.overlap(a, b).cpu().numpy() / g.dv
+            if dtype == np.float64:
+                assert np.max(np.abs(S - want)) <= 1e-13 * np.max(scale)
+            else:
+                assert np.all(np.abs(S - want) <= 2.0 ** -16 * scale)
